@@ -1,0 +1,188 @@
+/*
+ * iss.h -- C ABI of the MI355X (gfx950) matrix-free Stokes hot path.
+ *
+ * Method: Huber, Ruede, Waluga, Wohlmuth, "Highly sparse surface couplings
+ * for subdomain-wise isoviscous Stokes finite element discretizations"
+ * (arXiv:1604.07994).  Stabilised P1-P1 Stokes on uniformly refined
+ * simplicial macro meshes (Kuhn lattices), piecewise constant viscosity,
+ * homogeneous Dirichlet velocity on the whole boundary.  The viscous block
+ * is one of
+ *   ISS_GRADIENT   (mu grad u, grad v) everywhere (Sec. 1; inconsistent),
+ *   ISS_STRAIN     a_sym = (2 mu sym grad u, sym grad v)   (eq. standard),
+ *   ISS_INTERFACE  a_tr = a_sym - (mu div u, div v)        (eq. newbil),
+ *                  applied as in eq. equivalence-stencil: the decoupled
+ *                  Laplacian stencil per component on isoviscous rows and
+ *                  the full a_tr rows only at interface vertices.
+ * The saddle-point matrix is K = [[A, B^T], [B, -C]] (Sec. 5) with the
+ * weak divergence b(v, q) = -(div v, q) (eq. weaks) and the pressure
+ * stabilisation c(p, q) = sum_T beta h^2 / mu_T (grad p, grad q)_T.
+ *
+ * Vector layout (every vector argument).  A level with n cells per axis has
+ * N = (n+1)^d lattice vertices, vertex v = i + (n+1) (j + (n+1) k), x
+ * fastest, coordinates (i, j, k) / n on the unit cube (square).  A vector
+ * is d+1 contiguous fields [u_1 | ... | u_d | p], each of length N, so
+ * (d+1) N elements in total.  Velocity entries of boundary vertices are
+ * Dirichlet values: inputs must hold 0 there and outputs hold 0 there.
+ * Pressure lives on every vertex.  Element type: double for ISS_FP64,
+ * float for ISS_FP32 (see each call).
+ *
+ * Memory ownership.  Vector arguments are device pointers owned by the
+ * caller (any allocator; 8-byte aligned).  The library allocates and owns
+ * its metadata and internal work vectors (hipMalloc at create time, and
+ * for the Krylov basis at the first solve); iss_problem_destroy frees them.
+ *
+ * Streams.  Every call enqueues its kernels on the given stream and returns
+ * without synchronising, except calls that return host scalars
+ * (iss_residual with norms, iss_dot, iss_solve), which synchronise that
+ * stream before returning.
+ *
+ * Errors.  Every int-returning call returns ISS_OK (0) or a negative code;
+ * iss_last_error() gives a message for the calling thread.  No C++
+ * exception crosses the ABI.
+ */
+#ifndef ISS_H
+#define ISS_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* iss_stream_t; /* same type as hipStream_t */
+
+typedef struct iss_problem iss_problem;   /* opaque, library owned */
+
+enum iss_status {
+    ISS_OK = 0,
+    ISS_E_INVAL = -1,     /* bad argument (form, level, size, pointer)      */
+    ISS_E_HIP = -2,       /* a HIP runtime call failed                      */
+    ISS_E_NOTCONV = -3,   /* maxit reached before the tolerance; info set   */
+    ISS_E_DIVERGED = -4,  /* residual grew by more than 1e3 or is NaN/Inf   */
+    ISS_E_NOMEM = -5      /* device or host allocation failed               */
+};
+
+enum iss_form { ISS_GRADIENT = 0, ISS_STRAIN = 1, ISS_INTERFACE = 2 };
+enum iss_block { ISS_VELOCITY_ONLY = 0, ISS_FULL_STOKES = 1 };
+enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1 };
+enum iss_outer { ISS_OUTER_RICHARDSON = 0, ISS_OUTER_FGMRES = 1 };
+enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1 };
+
+/* A viscosity inclusion.  Sphere: a = (cx, cy, cz, r), region |x-c| < r
+ * (cz ignored in 2D).  Half-space: a = (axis, threshold, -, -), region
+ * x[axis] < threshold.  An element takes the phase of the first inclusion
+ * (array order) whose region contains its centroid, else phase 0 (the
+ * unresolved-interface setting of the remark closing Sec. 2.2). */
+typedef struct {
+    int kind;
+    int phase;            /* 1..nphase-1 */
+    double a[4];
+} iss_inclusion;
+
+typedef struct {
+    int nu1, nu2;         /* pre/post Uzawa smoothing steps (3, 3; Sec. 5)  */
+    double omega;         /* pressure under-relaxation (0.3; Sec. 5)        */
+    double stab_beta;     /* stabilisation constant beta (1/12)             */
+    int outer;            /* ISS_OUTER_RICHARDSON or ISS_OUTER_FGMRES       */
+    int restart;          /* FGMRES restart length (default 40)             */
+} iss_options;
+
+typedef struct {
+    int iterations;       /* V-cycles (= outer iterations) performed        */
+    double relres;        /* final ||b - K x||_2 / ||b||_2 (FP64)           */
+    double seconds;       /* wall time of the solve (host clock, synced)    */
+    int history_len;      /* entries written to history                     */
+    double* history;      /* optional host array (maxit+1) of relres, or 0  */
+} iss_solve_info;
+
+/* Fill *opt with the defaults above.  Returns ISS_OK. */
+int iss_default_options(iss_options* opt);
+
+/* Create a problem: dim in {2, 3}; the unit cube (square) as macro^d
+ * cubes x 6 Kuhn tetrahedra (squares x 2 triangles) refined `levels`
+ * times (finest level: n = macro * 2^levels cells per axis), with
+ * multigrid levels coarse_level..levels (coarse_level >= 1).  Viscosity
+ * mu[phase] > 0 for phase 0..nphase-1 (nphase <= 254).  Setup (element
+ * classification, interface lists, element tables, coarse factorisation)
+ * runs on the host and device 0 of the current HIP device.
+ * opt may be NULL for defaults.  *out receives the handle. */
+int iss_problem_create(int dim, int macro, int levels, int coarse_level,
+                       const iss_inclusion* inclusions, int ninclusions,
+                       const double* mu, int nphase, const iss_options* opt,
+                       iss_problem** out);
+void iss_problem_destroy(iss_problem* p);
+
+/* Number of lattice vertices N of `level`; a vector has (dim+1) N entries. */
+int iss_num_vertices(const iss_problem* p, int level, int64_t* n);
+
+/* Per-vertex class of `level` into host array cls (N bytes): bit 0 set for
+ * interface vertices (incident element viscosities differ), bit 1 for
+ * boundary vertices.  Counts go to *ninterface / *nboundary if non-NULL. */
+int iss_vertex_class(const iss_problem* p, int level, uint8_t* cls,
+                     int64_t* ninterface, int64_t* nboundary);
+
+/* Buoyancy load b = (0, .., 0, -rho sum_{T in buoyant phases} |T|/(d+1), 0)
+ * (body force (0,..,0,-rho) on elements of the listed phases) at `level`
+ * into device FP64 vector b (overwritten). */
+int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
+                     double rho, double* b, iss_stream_t stream);
+
+/* y = K x (block ISS_FULL_STOKES) or y = (A x_u, 0) (ISS_VELOCITY_ONLY) at
+ * `level` with the viscous form `form`.  prec selects the element type of
+ * x and y (double / float); accumulation in that type. */
+int iss_apply(iss_problem* p, int form, int block, int level, int prec,
+              const void* x, void* y, iss_stream_t stream);
+
+/* r = b - K x at `level`.  If norms is non-NULL it receives d+2 FP64
+ * numbers: the Euclidean norm of each field of r and of all of r (the
+ * call then synchronises). */
+int iss_residual(iss_problem* p, int form, int level, int prec, const void* x,
+                 const void* b, void* r, double* norms, iss_stream_t stream);
+
+/* nsteps Uzawa smoothing steps (eq. Uzawa_smooth) in place on x with
+ * right-hand side b: symmetric multicolour Gauss-Seidel on the velocity
+ * (colours (i+j+k) mod (d+1) forward with components 1..d, then the exact
+ * reverse), then delta from one forward colour-ordered Gauss-Seidel sweep
+ * on C started from 0 for B u - C p - g, and p += omega delta. */
+int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps,
+               void* x, const void* b, iss_stream_t stream);
+
+/* Grid transfers between `level` (fine) and level-1: restriction
+ * rc = P^T rf (velocity zero on coarse boundary vertices) and
+ * xf += P ec, P = P1 interpolation between the nested lattices. */
+int iss_restrict(iss_problem* p, int level, int prec, const void* rf, void* rc,
+                 iss_stream_t stream);
+int iss_prolong_add(iss_problem* p, int level, int prec, const void* ec, void* xf,
+                    iss_stream_t stream);
+
+/* Direct solve on the coarsest level: x = K_c^+ b with sum_j w_j p_j = 0,
+ * w_j = int mu^{-1} lambda_j (the space Q of Sec. 1).  FP64 always. */
+int iss_coarse_solve(iss_problem* p, int form, const double* b, double* x,
+                     iss_stream_t stream);
+
+/* One V(nu1, nu2) cycle on the finest level, in place on x. */
+int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b,
+               iss_stream_t stream);
+
+/* Solve K x = b on the finest level to ||b - K x|| <= rtol ||b|| from the
+ * initial guess in x (FP64 vectors).  The outer iteration (options) is
+ * Richardson with one V-cycle per step, or right-preconditioned FGMRES
+ * with one V-cycle as preconditioner.  prec = ISS_FP32 runs the V-cycle
+ * (stencil applies, smoothers, transfers) in FP32 while the outer
+ * residual, orthogonalisation, solution update and the coarsest solve
+ * stay FP64.  info may be NULL. */
+int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
+              const double* b, iss_solve_info* info, iss_stream_t stream);
+
+/* Euclidean dot product of two FP64 device vectors of length n. */
+int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double* out,
+            iss_stream_t stream);
+
+/* Message describing the last error on the calling thread. */
+const char* iss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISS_H */

@@ -1,0 +1,251 @@
+"""Thin ctypes binding of libiss.so (include/iss.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Torch
+tensors provide device memory and the current HIP stream.  If the library
+is missing this module raises; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libiss.so")
+
+FORMS = {"gradient": 0, "strain": 1, "interface": 2}
+BLOCKS = {"velocity": 0, "full": 1}
+OUTER = {"richardson": 0, "fgmres": 1}
+PREC_F64, PREC_F32 = 0, 1
+
+_lib = None
+
+
+class IssError(RuntimeError):
+    pass
+
+
+class Inclusion(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("phase", ctypes.c_int), ("a", ctypes.c_double * 4)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
+                ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("relres", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("history_len", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "iss_num_vertices",
+           "iss_vertex_class", "iss_rhs_buoyancy", "iss_apply", "iss_residual", "iss_smooth",
+           "iss_restrict", "iss_prolong_add", "iss_coarse_solve", "iss_vcycle", "iss_solve",
+           "iss_dot", "iss_last_error"]
+
+
+def lib():
+    """Load libiss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise IssError("libiss.so not built: run python -m paper_1604_07994_amd.build")
+    # torch ships its own HIP runtime (same soname libamdhip64.so.7); load it
+    # first so that libiss binds to that one runtime and torch's device
+    # memory and stream handles are valid inside the library.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, cint, cdbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.iss_last_error.restype = ctypes.c_char_p
+    L.iss_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.iss_problem_create.argtypes = [cint, cint, cint, cint, ctypes.POINTER(Inclusion), cint,
+                                     ctypes.POINTER(cdbl), cint, ctypes.POINTER(Options),
+                                     ctypes.POINTER(vp)]
+    L.iss_problem_destroy.argtypes = [vp]
+    L.iss_problem_destroy.restype = None
+    L.iss_num_vertices.argtypes = [vp, cint, ctypes.POINTER(i64)]
+    L.iss_vertex_class.argtypes = [vp, cint, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.iss_rhs_buoyancy.argtypes = [vp, cint, ctypes.POINTER(cint), cint, cdbl, vp, vp]
+    L.iss_apply.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
+    L.iss_residual.argtypes = [vp, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl), vp]
+    L.iss_smooth.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
+    L.iss_restrict.argtypes = [vp, cint, cint, vp, vp, vp]
+    L.iss_prolong_add.argtypes = [vp, cint, cint, vp, vp, vp]
+    L.iss_coarse_solve.argtypes = [vp, cint, vp, vp, vp]
+    L.iss_vcycle.argtypes = [vp, cint, cint, vp, vp, vp]
+    L.iss_solve.argtypes = [vp, cint, cint, cdbl, cint, vp, vp, ctypes.POINTER(SolveInfo), vp]
+    L.iss_dot.argtypes = [vp, vp, vp, i64, ctypes.POINTER(cdbl), vp]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise IssError("libiss error %d: %s" % (rc, lib().iss_last_error().decode()))
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _prec(t):
+    import torch
+    if t.dtype == torch.float64:
+        return PREC_F64
+    if t.dtype == torch.float32:
+        return PREC_F32
+    raise ValueError("vectors must be float64 or float32")
+
+
+def inclusions_to_c(inclusions):
+    arr = (Inclusion * max(1, len(inclusions)))()
+    for i, inc in enumerate(inclusions):
+        if inc["kind"] == "sphere":
+            c = list(inc["center"]) + [0.0] * (3 - len(inc["center"]))
+            arr[i].kind, arr[i].phase = 0, int(inc["phase"])
+            arr[i].a[:] = [c[0], c[1], c[2], inc["radius"]]
+        elif inc["kind"] == "halfspace":
+            arr[i].kind, arr[i].phase = 1, int(inc["phase"])
+            arr[i].a[:] = [float(inc["axis"]), inc["threshold"], 0.0, 0.0]
+        else:
+            raise ValueError(inc["kind"])
+    return arr
+
+
+class Problem:
+    """A refined Kuhn-lattice Stokes problem owned by libiss."""
+
+    def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
+                 stab_beta=1.0 / 12.0, outer="richardson", restart=40):
+        L = lib()
+        self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
+        opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart)
+        incs = inclusions_to_c(inclusions)
+        mu_arr = (ctypes.c_double * len(mu))(*mu)
+        h = ctypes.c_void_p()
+        _check(L.iss_problem_create(dim, macro, levels, coarse, incs, len(inclusions), mu_arr,
+                                    len(mu), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"], **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iss_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- sizes ------------------------------------------------------------
+    def num_vertices(self, level=None):
+        level = self.levels if level is None else level
+        n = ctypes.c_int64()
+        _check(lib().iss_num_vertices(self._h, level, ctypes.byref(n)))
+        return n.value
+
+    def vector_size(self, level=None):
+        return (self.dim + 1) * self.num_vertices(level)
+
+    def vertex_class(self, level=None):
+        level = self.levels if level is None else level
+        cls = np.zeros(self.num_vertices(level), dtype=np.uint8)
+        ni, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().iss_vertex_class(self._h, level, cls.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(ni), ctypes.byref(nb)))
+        return cls, ni.value, nb.value
+
+    def _vec(self, t, level, dtype=None):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+            raise ValueError("expected a contiguous CUDA (HIP) tensor")
+        if t.numel() != self.vector_size(level):
+            raise ValueError("vector has %d entries, level needs %d" % (t.numel(), self.vector_size(level)))
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError("expected dtype %s" % dtype)
+        return ctypes.c_void_p(t.data_ptr())
+
+    # -- operators --------------------------------------------------------
+    def rhs_buoyancy(self, b, phases, rho=1.0, level=None):
+        import torch
+        level = self.levels if level is None else level
+        ph = (ctypes.c_int * max(1, len(phases)))(*phases)
+        _check(lib().iss_rhs_buoyancy(self._h, level, ph, len(phases), rho,
+                                      self._vec(b, level, torch.float64), _stream()))
+        return b
+
+    def apply(self, form, x, y, level=None, block="full"):
+        level = self.levels if level is None else level
+        if x.dtype != y.dtype:
+            raise ValueError("x and y must share a dtype")
+        _check(lib().iss_apply(self._h, FORMS[form], BLOCKS[block], level, _prec(x),
+                               self._vec(x, level), self._vec(y, level), _stream()))
+        return y
+
+    def residual(self, form, x, b, r, level=None, norms=False):
+        level = self.levels if level is None else level
+        out = (ctypes.c_double * (self.dim + 2))() if norms else None
+        _check(lib().iss_residual(self._h, FORMS[form], level, _prec(x), self._vec(x, level),
+                                  self._vec(b, level), self._vec(r, level), out, _stream()))
+        return list(out) if norms else r
+
+    def smooth(self, form, x, b, nsteps=1, level=None):
+        level = self.levels if level is None else level
+        _check(lib().iss_smooth(self._h, FORMS[form], level, _prec(x), nsteps,
+                                self._vec(x, level), self._vec(b, level), _stream()))
+        return x
+
+    def restrict(self, rf, rc, level=None):
+        level = self.levels if level is None else level
+        _check(lib().iss_restrict(self._h, level, _prec(rf), self._vec(rf, level),
+                                  self._vec(rc, level - 1), _stream()))
+        return rc
+
+    def prolong_add(self, ec, xf, level=None):
+        level = self.levels if level is None else level
+        _check(lib().iss_prolong_add(self._h, level, _prec(xf), self._vec(ec, level - 1),
+                                     self._vec(xf, level), _stream()))
+        return xf
+
+    def coarse_solve(self, form, b, x):
+        import torch
+        _check(lib().iss_coarse_solve(self._h, FORMS[form], self._vec(b, self.coarse, torch.float64),
+                                      self._vec(x, self.coarse, torch.float64), _stream()))
+        return x
+
+    def vcycle(self, form, x, b):
+        _check(lib().iss_vcycle(self._h, FORMS[form], _prec(x), self._vec(x, self.levels),
+                                self._vec(b, self.levels), _stream()))
+        return x
+
+    def solve(self, form, x, b, prec="fp64", rtol=1e-8, maxit=200, raise_on_fail=True):
+        import torch
+        hist = (ctypes.c_double * (maxit + 1))()
+        info = SolveInfo(0, 0.0, 0.0, 0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)))
+        rc = lib().iss_solve(self._h, FORMS[form], PREC_F64 if prec == "fp64" else PREC_F32, rtol,
+                             maxit, self._vec(x, self.levels, torch.float64),
+                             self._vec(b, self.levels, torch.float64), ctypes.byref(info), _stream())
+        if rc != 0 and raise_on_fail:
+            _check(rc)
+        return {"status": rc, "iterations": info.iterations, "relres": info.relres,
+                "seconds": info.seconds, "history": [hist[i] for i in range(info.history_len)]}
+
+    def dot(self, a, b):
+        import torch
+        for t in (a, b):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64):
+                raise ValueError("dot needs contiguous float64 CUDA tensors")
+        if a.numel() != b.numel():
+            raise ValueError("size mismatch")
+        out = ctypes.c_double()
+        _check(lib().iss_dot(self._h, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                             a.numel(), ctypes.byref(out), _stream()))
+        return out.value

@@ -1,0 +1,124 @@
+// Compile-time geometry of the Kuhn (Freudenthal) lattice.
+//
+// The uniformly refined cube macro meshes of the paper (six tetrahedra per
+// cube, Sec. 4; Bey refinement, Sec. 3 remark) are Kuhn lattices: every
+// lattice cell holds the d! simplices x0, x0+e_pi(0), x0+e_pi(0)+e_pi(1),
+// ..., x0+(1..1), one per permutation pi.  Around a vertex these tables
+// give
+//   * the stencil footprint: the centre and +-w for the 2^d - 1 nonzero
+//     0/1 vectors w (15 points in 3D, 7 in 2D),
+//   * the incident elements ("slots"): element type pi and local index a of
+//     the vertex in it (d! (d+1) slots: 24 in 3D, 6 in 2D), and for each
+//     slot the footprint index of each element vertex.
+// Everything is constexpr so that fully unrolled kernel loops index
+// register arrays with constants.
+#pragma once
+
+namespace iss {
+
+template <int D> struct Kuhn;
+
+template <int D>
+struct KuhnTables {
+    static constexpr int NB = (D == 3) ? 15 : 7;              // footprint
+    static constexpr int NT = (D == 3) ? 6 : 2;               // element types
+    static constexpr int NS = NT * (D + 1);                   // slots
+    int off[NB][3];          // footprint offsets (z = 0 in 2D)
+    int type_vert[NT][D + 1][3];   // Kuhn simplex vertices of each type
+    int slot_type[NS];
+    int slot_loc[NS];
+    int slot_nb[NS][D + 1];  // footprint index of each element vertex
+    int slot_cell[NS][3];    // cell origin relative to the vertex
+};
+
+namespace detail {
+
+template <int D>
+constexpr int find_off(const KuhnTables<D>& t, int x, int y, int z) {
+    for (int o = 0; o < KuhnTables<D>::NB; ++o)
+        if (t.off[o][0] == x && t.off[o][1] == y && t.off[o][2] == z) return o;
+    return -1;
+}
+
+template <int D>
+constexpr KuhnTables<D> make_tables() {
+    KuhnTables<D> t{};
+    // footprint: centre, then +w, -w for w = e1, e2, (e3), e1+e2, (e1+e3,
+    // e2+e3, e1+e2+e3)
+    int ws[7][3] = {};
+    int nw = 0;
+    if (D == 3) {
+        int w3[7][3] = {{1,0,0},{0,1,0},{0,0,1},{1,1,0},{1,0,1},{0,1,1},{1,1,1}};
+        for (int i = 0; i < 7; ++i) for (int a = 0; a < 3; ++a) ws[i][a] = w3[i][a];
+        nw = 7;
+    } else {
+        int w2[3][3] = {{1,0,0},{0,1,0},{1,1,0}};
+        for (int i = 0; i < 3; ++i) for (int a = 0; a < 3; ++a) ws[i][a] = w2[i][a];
+        nw = 3;
+    }
+    for (int a = 0; a < 3; ++a) t.off[0][a] = 0;
+    for (int i = 0; i < nw; ++i)
+        for (int a = 0; a < 3; ++a) {
+            t.off[1 + 2 * i][a] = ws[i][a];
+            t.off[2 + 2 * i][a] = -ws[i][a];
+        }
+    // element types: permutations in lexicographic order
+    int perms3[6][3] = {{0,1,2},{0,2,1},{1,0,2},{1,2,0},{2,0,1},{2,1,0}};
+    int perms2[2][3] = {{0,1,0},{1,0,0}};
+    for (int ty = 0; ty < KuhnTables<D>::NT; ++ty) {
+        int cur[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) t.type_vert[ty][0][a] = 0;
+        for (int s = 0; s < D; ++s) {
+            int ax = (D == 3) ? perms3[ty][s] : perms2[ty][s];
+            cur[ax] += 1;
+            for (int a = 0; a < 3; ++a) t.type_vert[ty][s + 1][a] = cur[a];
+        }
+    }
+    // slots: (type, local index)
+    int s = 0;
+    for (int ty = 0; ty < KuhnTables<D>::NT; ++ty)
+        for (int loc = 0; loc <= D; ++loc) {
+            t.slot_type[s] = ty;
+            t.slot_loc[s] = loc;
+            for (int a = 0; a < 3; ++a) t.slot_cell[s][a] = -t.type_vert[ty][loc][a];
+            for (int b = 0; b <= D; ++b)
+                t.slot_nb[s][b] = find_off<D>(t,
+                    t.type_vert[ty][b][0] - t.type_vert[ty][loc][0],
+                    t.type_vert[ty][b][1] - t.type_vert[ty][loc][1],
+                    t.type_vert[ty][b][2] - t.type_vert[ty][loc][2]);
+            ++s;
+        }
+    return t;
+}
+
+}  // namespace detail
+
+template <> struct Kuhn<3> {
+    static constexpr KuhnTables<3> T = detail::make_tables<3>();
+};
+template <> struct Kuhn<2> {
+    static constexpr KuhnTables<2> T = detail::make_tables<2>();
+};
+
+// Floating-point element tables for the unit lattice (h = 1); per level the
+// viscous block scales with h^(d-2), B with h^(d-1) and C with beta h^d.
+//   Avis[f][type][a*D+l][b*D+k]: viscous form f (0 gradient, 1 strain,
+//       2 a_tr) between test phi_a e_l and trial phi_b e_k, viscosity 1;
+//   Bel[type][a][b*D+k]: -(div(phi_b e_k), lambda_a)_T;
+//   Cel[type][a][b]: (grad lambda_b, grad lambda_a)_T;
+// and the stencils of an isoviscous interior vertex (viscosity 1):
+//   Svis[f][l][k][o], Sbt[l][o] (B^T), Sdiv[k][o] (B), Sc[o] (C / beta).
+template <int D, typename C>
+struct ElemTables {
+    static constexpr int NB = KuhnTables<D>::NB;
+    static constexpr int NT = KuhnTables<D>::NT;
+    C Avis[3][NT][(D + 1) * D][(D + 1) * D];
+    C Bel[NT][D + 1][(D + 1) * D];
+    C Cel[NT][D + 1][D + 1];
+    C Svis[3][D][D][NB];
+    C Sbt[D][NB];
+    C Sdiv[D][NB];
+    C Sc[NB];
+};
+
+}  // namespace iss

@@ -1,0 +1,972 @@
+// Host side of the Stokes hot path: problem setup (element classification,
+// interface lists, element tables, coarse factorisation), the multigrid and
+// Krylov orchestration, and the C ABI declared in include/iss.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/iss.h"
+#include "iss_internal.h"
+
+using namespace iss;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define ISS_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ISS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// element tables of the unit lattice (h = 1)
+
+// Barycentric gradients of a simplex: with M = [1 | X] (row i = [1, x_i]),
+// lambda(x) = [1, x] M^{-1}; gradient of lambda_i = rows 1..d of column i.
+template <int D>
+void simplex_gradients(const int (&X)[D + 1][3], double (&g)[D + 1][D], double& vol) {
+    double M[D + 1][D + 1], Inv[D + 1][D + 1];
+    for (int i = 0; i <= D; ++i) {
+        M[i][0] = 1.0;
+        for (int a = 0; a < D; ++a) M[i][a + 1] = X[i][a];
+        for (int j = 0; j <= D; ++j) Inv[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    double det = 1.0;
+    for (int c = 0; c <= D; ++c) {          // Gauss-Jordan with partial pivoting
+        int piv = c;
+        for (int r = c + 1; r <= D; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j <= D; ++j) { std::swap(M[c][j], M[piv][j]); std::swap(Inv[c][j], Inv[piv][j]); }
+            det = -det;
+        }
+        const double d = M[c][c];
+        det *= d;
+        for (int j = 0; j <= D; ++j) { M[c][j] /= d; Inv[c][j] /= d; }
+        for (int r = 0; r <= D; ++r) {
+            if (r == c) continue;
+            const double f = M[r][c];
+            for (int j = 0; j <= D; ++j) { M[r][j] -= f * M[c][j]; Inv[r][j] -= f * Inv[c][j]; }
+        }
+    }
+    for (int i = 0; i <= D; ++i)
+        for (int a = 0; a < D; ++a) g[i][a] = Inv[a + 1][i];
+    double fact = 1.0;
+    for (int a = 2; a <= D; ++a) fact *= a;
+    vol = std::fabs(det) / fact;
+}
+
+template <int D>
+int build_tables(ElemTables<D, double>& t) {
+    constexpr auto& K = Kuhn<D>::T;
+    constexpr int NT = KuhnTables<D>::NT, NS = KuhnTables<D>::NS, NB = KuhnTables<D>::NB;
+    std::memset(&t, 0, sizeof(t));
+    for (int ty = 0; ty < NT; ++ty) {
+        int X[D + 1][3];
+        for (int b = 0; b <= D; ++b)
+            for (int a = 0; a < 3; ++a) X[b][a] = K.type_vert[ty][b][a];
+        double g[D + 1][D], vol;
+        simplex_gradients<D>(X, g, vol);
+        for (int a = 0; a <= D; ++a)          // test vertex
+            for (int b = 0; b <= D; ++b) {    // trial vertex
+                double gg = 0;
+                for (int q = 0; q < D; ++q) gg += g[a][q] * g[b][q];
+                t.Cel[ty][a][b] = vol * gg;
+                for (int l = 0; l < D; ++l)
+                    for (int k = 0; k < D; ++k) {
+                        // (mu grad(phi_b e_k), grad(phi_a e_l)) with mu = 1
+                        const double lap = (k == l) ? vol * gg : 0.0;
+                        // 2 sym(grad)(trial) : sym(grad)(test)
+                        const double sym = lap + vol * g[b][l] * g[a][k];
+                        // (div trial, div test)
+                        const double dv = vol * g[b][k] * g[a][l];
+                        t.Avis[FORM_GRADIENT][ty][a * D + l][b * D + k] = lap;
+                        t.Avis[FORM_STRAIN][ty][a * D + l][b * D + k] = sym;
+                        t.Avis[FORM_INTERFACE][ty][a * D + l][b * D + k] = sym - dv;
+                    }
+                // -(div(phi_b e_k), lambda_a) with int lambda_a = vol / (d+1)
+                for (int k = 0; k < D; ++k) t.Bel[ty][a][b * D + k] = -vol / (D + 1) * g[b][k];
+            }
+    }
+    // stencils of an interior vertex with all incident elements present
+    for (int s = 0; s < NS; ++s) {
+        const int ty = K.slot_type[s], a = K.slot_loc[s];
+        for (int b = 0; b <= D; ++b) {
+            const int o = K.slot_nb[s][b];
+            if (o < 0) return fail(ISS_E_INVAL, "geometry table: element vertex outside footprint");
+            for (int f = 0; f < 3; ++f)
+                for (int l = 0; l < D; ++l)
+                    for (int k = 0; k < D; ++k) t.Svis[f][l][k][o] += t.Avis[f][ty][a * D + l][b * D + k];
+            for (int l = 0; l < D; ++l) t.Sbt[l][o] += t.Bel[ty][b][a * D + l];
+            for (int k = 0; k < D; ++k) t.Sdiv[k][o] += t.Bel[ty][a][b * D + k];
+            t.Sc[o] += t.Cel[ty][a][b];
+        }
+    }
+    // the bulk kernels rely on the decoupled structure of isoviscous rows:
+    // a_tr rows equal Laplacian rows (eq. equivalence-stencil), no coupling
+    // between components, no weight on the diagonal directions, and the
+    // same for C.
+    for (int l = 0; l < D; ++l)
+        for (int k = 0; k < D; ++k)
+            for (int o = 0; o < NB; ++o) {
+                const double lap = t.Svis[0][l][k][o], tr = t.Svis[2][l][k][o];
+                if (std::fabs(lap - tr) > 1e-13) return fail(ISS_E_INVAL, "a_tr bulk stencil != Laplacian");
+                if ((k != l || o > 2 * D) && std::fabs(lap) > 1e-13)
+                    return fail(ISS_E_INVAL, "Laplacian stencil not decoupled / axis-only");
+                t.Svis[2][l][k][o] = lap;   // identical by construction
+            }
+    for (int o = 2 * D + 1; o < NB; ++o)
+        if (std::fabs(t.Sc[o]) > 1e-13) return fail(ISS_E_INVAL, "C stencil not axis-only");
+    return ISS_OK;
+}
+
+template <int D>
+void to_float(const ElemTables<D, double>& a, ElemTables<D, float>& b) {
+    const double* s = reinterpret_cast<const double*>(&a);
+    float* d = reinterpret_cast<float*>(&b);
+    const size_t n = sizeof(a) / sizeof(double);
+    for (size_t i = 0; i < n; ++i) d[i] = (float)s[i];
+}
+
+// ----------------------------------------------------------------------------
+// problem data
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Level {
+    LevelView v{};
+    uint8_t* d_vphase = nullptr;
+    int32_t* d_spec = nullptr;
+    uint8_t* d_spec_eph = nullptr;
+    std::vector<uint8_t> cls;       // per vertex: bit0 interface, bit1 boundary
+    std::vector<uint8_t> elem_phase;// per element (cell * NT + type)
+    int64_t ninterface = 0, nboundary = 0;
+    void* w_x[2] = {nullptr, nullptr};
+    void* w_b[2] = {nullptr, nullptr};
+    void* w_r[2] = {nullptr, nullptr};
+};
+
+struct Coarse {
+    int64_t M = 0;                  // free dofs + 1 (border)
+    std::vector<int32_t> free_idx;
+    int32_t* d_free = nullptr;
+    double* d_Kinv[3] = {nullptr, nullptr, nullptr};
+    double* d_bc = nullptr;
+    double* d_xc = nullptr;
+};
+
+}  // namespace
+
+struct iss_problem {
+    int dim = 3, macro = 1, levels = 0, coarse = 0;
+    std::vector<iss_inclusion> inc;
+    std::vector<double> mu;
+    iss_options opt{};
+    std::vector<Level> lv;          // index = level
+    double* d_mu64 = nullptr;
+    double* d_imu64 = nullptr;
+    float* d_mu32 = nullptr;
+    float* d_imu32 = nullptr;
+    Coarse cs;
+    ElemTables<3, double> t3{};
+    ElemTables<2, double> t2{};
+    // reductions
+    double* d_partial = nullptr;    // 1024 * 64 doubles
+    double* d_red = nullptr;        // 64 doubles
+    // Krylov workspace (finest level, FP64)
+    int kry_m = 0;
+    double* d_V = nullptr;
+    double* d_Z = nullptr;
+    double* d_w = nullptr;
+    double* d_r = nullptr;
+    double* d_h = nullptr;          // m + 2 entries
+    uint8_t* d_flag = nullptr;      // 256 buoyancy flags
+    double* h_pinned = nullptr;     // 8192 doubles of pinned host memory
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+int dev_alloc(iss_problem* p, void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return fail(ISS_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    p->allocs.push_back(*ptr);
+    return ISS_OK;
+}
+
+template <typename T>
+int dev_upload(iss_problem* p, T** ptr, const T* host, size_t count) {
+    int rc = dev_alloc(p, (void**)ptr, count * sizeof(T));
+    if (rc) return rc;
+    if (count) ISS_HIP(hipMemcpy(*ptr, host, count * sizeof(T), hipMemcpyHostToDevice));
+    return ISS_OK;
+}
+
+// phase of an element by the centroid rule
+int element_phase(const iss_problem* p, const double (&c)[3]) {
+    for (const auto& in : p->inc) {
+        bool inside;
+        if (in.kind == ISS_SPHERE) {
+            double r2 = 0;
+            for (int a = 0; a < p->dim; ++a) r2 += (c[a] - in.a[a]) * (c[a] - in.a[a]);
+            inside = r2 < in.a[3] * in.a[3];
+        } else {
+            inside = c[(int)in.a[0]] < in.a[1];
+        }
+        if (inside) return in.phase;
+    }
+    return 0;
+}
+
+template <int D>
+int setup_level(iss_problem* p, int l) {
+    constexpr auto& K = Kuhn<D>::T;
+    constexpr int NT = KuhnTables<D>::NT, NS = KuhnTables<D>::NS;
+    Level& L = p->lv[l];
+    const int n = p->macro << l;
+    const int64_t n1 = n + 1;
+    const int64_t N = (D == 3) ? n1 * n1 * n1 : n1 * n1;
+    const int64_t ncell = (D == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+    // element phases
+    L.elem_phase.assign(ncell * NT, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < ncell; ++c) {
+        const int ci = (int)(c % n), cj = (int)((c / n) % n), ck = (D == 3) ? (int)(c / ((int64_t)n * n)) : 0;
+        for (int ty = 0; ty < NT; ++ty) {
+            double cen[3] = {0, 0, 0};
+            for (int b = 0; b <= D; ++b) {
+                cen[0] += ci + K.type_vert[ty][b][0];
+                cen[1] += cj + K.type_vert[ty][b][1];
+                cen[2] += ck + K.type_vert[ty][b][2];
+            }
+            for (int a = 0; a < 3; ++a) cen[a] /= (double)(D + 1) * n;
+            L.elem_phase[c * NT + ty] = (uint8_t)element_phase(p, cen);
+        }
+    }
+    // vertex classes
+    std::vector<uint8_t> vphase(N);
+    L.cls.assign(N, 0);
+    std::vector<uint8_t> slotph((size_t)N * 0);   // built only for special vertices below
+    std::vector<std::vector<int32_t>> spec_by_col(D + 1);
+    std::vector<std::vector<uint8_t>> eph_by_col(D + 1);
+    int64_t nif = 0, nbd = 0;
+    const int nthr = 1;
+    (void)nthr;
+    for (int64_t v = 0; v < N; ++v) {
+        const int i = (int)(v % n1), j = (int)((v / n1) % n1), k = (D == 3) ? (int)(v / (n1 * n1)) : 0;
+        const int ijk[3] = {i, j, k};
+        bool bnd = false;
+        for (int a = 0; a < D; ++a) bnd = bnd || ijk[a] == 0 || ijk[a] == n;
+        uint8_t ph[NS];
+        int first = -1;
+        bool mixed_phase = false, mixed_mu = false;
+        for (int s = 0; s < NS; ++s) {
+            int cc[3];
+            bool in = true;
+            for (int a = 0; a < D; ++a) {
+                cc[a] = ijk[a] + K.slot_cell[s][a];
+                in = in && cc[a] >= 0 && cc[a] < n;
+            }
+            if (!in) { ph[s] = OUTSIDE; continue; }
+            const int64_t cell = (D == 3) ? cc[0] + (int64_t)n * (cc[1] + (int64_t)n * cc[2]) : cc[0] + (int64_t)n * cc[1];
+            ph[s] = L.elem_phase[cell * NT + K.slot_type[s]];
+            if (first < 0) first = ph[s];
+            else {
+                if (ph[s] != first) mixed_phase = true;
+                if (p->mu[ph[s]] != p->mu[first]) mixed_mu = true;
+            }
+        }
+        if (mixed_mu) { L.cls[v] |= 1; ++nif; }
+        if (bnd) { L.cls[v] |= 2; ++nbd; }
+        if (bnd || mixed_phase) {
+            vphase[v] = SPECIAL;
+            const int col = (i + j + k) % (D + 1);
+            spec_by_col[col].push_back((int32_t)v);
+            eph_by_col[col].insert(eph_by_col[col].end(), ph, ph + NS);
+        } else {
+            vphase[v] = (uint8_t)first;
+        }
+    }
+    L.ninterface = nif;
+    L.nboundary = nbd;
+    std::vector<int32_t> spec;
+    std::vector<uint8_t> eph;
+    int64_t off[5] = {0, 0, 0, 0, 0};
+    for (int c = 0; c <= D; ++c) {
+        off[c] = (int64_t)spec.size();
+        spec.insert(spec.end(), spec_by_col[c].begin(), spec_by_col[c].end());
+        eph.insert(eph.end(), eph_by_col[c].begin(), eph_by_col[c].end());
+    }
+    for (int c = D + 1; c < 5; ++c) off[c] = (int64_t)spec.size();
+    int rc;
+    if ((rc = dev_upload(p, &L.d_vphase, vphase.data(), vphase.size()))) return rc;
+    if ((rc = dev_upload(p, &L.d_spec, spec.data(), spec.size()))) return rc;
+    if ((rc = dev_upload(p, &L.d_spec_eph, eph.data(), eph.size()))) return rc;
+    LevelView& V = L.v;
+    V.dim = D;
+    V.n = n;
+    V.N = N;
+    V.sy = n1;
+    V.sz = (D == 3) ? n1 * n1 : 0;
+    V.vphase = L.d_vphase;
+    V.spec = L.d_spec;
+    V.spec_eph = L.d_spec_eph;
+    for (int c = 0; c < 5; ++c) V.spec_off[c] = off[c];
+    V.mu64 = p->d_mu64;
+    V.imu64 = p->d_imu64;
+    V.mu32 = p->d_mu32;
+    V.imu32 = p->d_imu32;
+    const double h = 1.0 / n;
+    V.sA = std::pow(h, D - 2);
+    V.sB = std::pow(h, D - 1);
+    V.sC = p->opt.stab_beta * std::pow(h, D);
+    return ISS_OK;
+}
+
+int ensure_work(iss_problem* p, int l, int prec) {
+    Level& L = p->lv[l];
+    if (L.w_x[prec]) return ISS_OK;
+    const size_t bytes = (size_t)(p->dim + 1) * L.v.N * (prec == PREC_F64 ? 8 : 4);
+    int rc;
+    if ((rc = dev_alloc(p, &L.w_x[prec], bytes))) return rc;
+    if ((rc = dev_alloc(p, &L.w_b[prec], bytes))) return rc;
+    if ((rc = dev_alloc(p, &L.w_r[prec], bytes))) return rc;
+    return ISS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// coarse level: dense bordered matrix, LU with partial pivoting, inverse
+
+template <int D>
+void coarse_matrix(const iss_problem* p, int form, std::vector<double>& Kd, int64_t& M,
+                   std::vector<int32_t>& free_idx) {
+    constexpr auto& K = Kuhn<D>::T;
+    constexpr int NT = KuhnTables<D>::NT;
+    const ElemTables<D, double>& E = *reinterpret_cast<const ElemTables<D, double>*>(
+        D == 3 ? (const void*)&p->t3 : (const void*)&p->t2);
+    const Level& L = p->lv[p->coarse];
+    const int n = L.v.n;
+    const int64_t n1 = n + 1, N = L.v.N;
+    // compact numbering of free dofs: velocity of interior vertices, all pressure
+    std::vector<int64_t> cmap((size_t)(D + 1) * N, -1);
+    free_idx.clear();
+    for (int f = 0; f <= D; ++f)
+        for (int64_t v = 0; v < N; ++v)
+            if (f == D || !(L.cls[v] & 2)) {
+                cmap[(size_t)f * N + v] = (int64_t)free_idx.size();
+                free_idx.push_back((int32_t)((int64_t)f * N + v));
+            }
+    const int64_t m = (int64_t)free_idx.size();
+    M = m + 1;
+    Kd.assign((size_t)M * M, 0.0);
+    const double sA = L.v.sA, sB = L.v.sB, sC = L.v.sC;
+    std::vector<double> w(N, 0.0);
+    const int64_t ncell = (D == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+    for (int64_t c = 0; c < ncell; ++c) {
+        const int ci = (int)(c % n), cj = (int)((c / n) % n), ck = (D == 3) ? (int)(c / ((int64_t)n * n)) : 0;
+        for (int ty = 0; ty < NT; ++ty) {
+            const int ph = L.elem_phase[c * NT + ty];
+            const double mu = p->mu[ph];
+            int64_t vid[D + 1];
+            for (int b = 0; b <= D; ++b)
+                vid[b] = (ci + K.type_vert[ty][b][0]) + n1 * (cj + K.type_vert[ty][b][1]) +
+                         (D == 3 ? n1 * n1 * (ck + K.type_vert[ty][b][2]) : 0);
+            double vol = 1.0;
+            for (int a = 0; a < D; ++a) vol /= n;
+            vol /= (D == 3 ? 6.0 : 2.0);
+            for (int a = 0; a <= D; ++a) {
+                w[vid[a]] += vol / ((D + 1) * mu);
+                for (int b = 0; b <= D; ++b) {
+                    // velocity-velocity and B^T / B couplings
+                    for (int l = 0; l < D; ++l) {
+                        const int64_t r = cmap[(size_t)l * N + vid[a]];
+                        if (r < 0) continue;
+                        for (int k = 0; k < D; ++k) {
+                            const int64_t cc = cmap[(size_t)k * N + vid[b]];
+                            if (cc >= 0) Kd[(size_t)r * M + cc] += mu * sA * E.Avis[form][ty][a * D + l][b * D + k];
+                        }
+                        const int64_t cp = cmap[(size_t)D * N + vid[b]];
+                        Kd[(size_t)r * M + cp] += sB * E.Bel[ty][b][a * D + l];
+                    }
+                    const int64_t rp = cmap[(size_t)D * N + vid[a]];
+                    for (int k = 0; k < D; ++k) {
+                        const int64_t cc = cmap[(size_t)k * N + vid[b]];
+                        if (cc >= 0) Kd[(size_t)rp * M + cc] += sB * E.Bel[ty][a][b * D + k];
+                    }
+                    Kd[(size_t)rp * M + cmap[(size_t)D * N + vid[b]]] -= sC / mu * E.Cel[ty][a][b];
+                }
+            }
+        }
+    }
+    for (int64_t v = 0; v < N; ++v) {
+        const int64_t cp = cmap[(size_t)D * N + v];
+        Kd[(size_t)cp * M + m] = w[v];
+        Kd[(size_t)m * M + cp] = w[v];
+    }
+}
+
+// In-place inverse of a dense M x M matrix (row major) by LU with partial
+// pivoting followed by column-wise triangular solves.
+int dense_inverse(std::vector<double>& A, int64_t M) {
+    std::vector<int64_t> piv(M);
+    for (int64_t c = 0; c < M; ++c) {
+        int64_t pr = c;
+        double best = std::fabs(A[(size_t)c * M + c]);
+        for (int64_t r = c + 1; r < M; ++r) {
+            const double v = std::fabs(A[(size_t)r * M + c]);
+            if (v > best) { best = v; pr = r; }
+        }
+        if (best == 0.0) return fail(ISS_E_INVAL, "coarse matrix is singular");
+        piv[c] = pr;
+        if (pr != c)
+            for (int64_t j = 0; j < M; ++j) std::swap(A[(size_t)c * M + j], A[(size_t)pr * M + j]);
+        const double d = A[(size_t)c * M + c];
+        const double* rowc = &A[(size_t)c * M];
+#pragma omp parallel for schedule(static)
+        for (int64_t r = c + 1; r < M; ++r) {
+            double* rowr = &A[(size_t)r * M];
+            const double f = rowr[c] / d;
+            rowr[c] = f;
+            for (int64_t j = c + 1; j < M; ++j) rowr[j] -= f * rowc[j];
+        }
+    }
+    // solve L U X = P I column by column
+    std::vector<double> Inv((size_t)M * M);
+#pragma omp parallel
+    {
+        std::vector<double> col(M);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t j = 0; j < M; ++j) {
+            std::fill(col.begin(), col.end(), 0.0);
+            col[j] = 1.0;
+            for (int64_t c = 0; c < M; ++c)
+                if (piv[c] != c) std::swap(col[c], col[piv[c]]);
+            for (int64_t r = 0; r < M; ++r) {
+                double s = col[r];
+                const double* a = &A[(size_t)r * M];
+                for (int64_t c = 0; c < r; ++c) s -= a[c] * col[c];
+                col[r] = s;
+            }
+            for (int64_t r = M - 1; r >= 0; --r) {
+                double s = col[r];
+                const double* a = &A[(size_t)r * M];
+                for (int64_t c = r + 1; c < M; ++c) s -= a[c] * col[c];
+                col[r] = s / a[r];
+            }
+            for (int64_t r = 0; r < M; ++r) Inv[(size_t)r * M + j] = col[r];
+        }
+    }
+    A.swap(Inv);
+    return ISS_OK;
+}
+
+int ensure_coarse(iss_problem* p, int form) {
+    Coarse& cs = p->cs;
+    if (cs.d_Kinv[form]) return ISS_OK;
+    std::vector<double> Kd;
+    int64_t M;
+    std::vector<int32_t> fidx;
+    if (p->dim == 3) coarse_matrix<3>(p, form, Kd, M, fidx);
+    else coarse_matrix<2>(p, form, Kd, M, fidx);
+    int rc;
+    if ((rc = dense_inverse(Kd, M))) return rc;
+    if (!cs.d_free) {
+        cs.M = M;
+        cs.free_idx = fidx;
+        if ((rc = dev_upload(p, &cs.d_free, fidx.data(), fidx.size()))) return rc;
+        if ((rc = dev_alloc(p, (void**)&cs.d_bc, M * sizeof(double)))) return rc;
+        if ((rc = dev_alloc(p, (void**)&cs.d_xc, M * sizeof(double)))) return rc;
+        ISS_HIP(hipMemset(cs.d_bc, 0, M * sizeof(double)));
+    }
+    if ((rc = dev_upload(p, &cs.d_Kinv[form], Kd.data(), Kd.size()))) return rc;
+    return ISS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// multigrid
+
+int check_form(int form) { return (form >= 0 && form <= 2) ? ISS_OK : fail(ISS_E_INVAL, "bad form"); }
+int check_prec(int prec) { return (prec == 0 || prec == 1) ? ISS_OK : fail(ISS_E_INVAL, "bad precision"); }
+int check_level(const iss_problem* p, int l) {
+    return (l >= p->coarse && l <= p->levels) ? ISS_OK : fail(ISS_E_INVAL, "level out of range");
+}
+
+int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hipStream_t s) {
+    int rc;
+    if ((rc = ensure_coarse(p, form))) return rc;
+    Coarse& cs = p->cs;
+    const Level& L = p->lv[p->coarse];
+    const int64_t m = cs.M - 1;
+    ISS_HIP(k_gather(prec, b, cs.d_free, m, cs.d_bc, s));
+    ISS_HIP(k_dense_matvec(cs.d_Kinv[form], cs.M, cs.d_bc, cs.d_xc, s));
+    ISS_HIP(k_fill(prec, x, (int64_t)(p->dim + 1) * L.v.N, 0.0, s));
+    ISS_HIP(k_scatter(prec, cs.d_xc, cs.d_free, m, x, s));
+    return ISS_OK;
+}
+
+int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, hipStream_t s) {
+    if (l == p->coarse) return coarse_solve(p, form, prec, b, x, s);
+    int rc;
+    if ((rc = ensure_work(p, l, prec)) || (rc = ensure_work(p, l - 1, prec))) return rc;
+    Level& L = p->lv[l];
+    Level& Lc = p->lv[l - 1];
+    const size_t es = prec == PREC_F64 ? 8 : 4;
+    void* delta = (char*)L.w_r[prec] + (size_t)p->dim * L.v.N * es;
+    for (int i = 0; i < p->opt.nu1; ++i)
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, delta, s));
+    ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
+    ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
+    ISS_HIP(k_fill(prec, Lc.w_x[prec], (int64_t)(p->dim + 1) * Lc.v.N, 0.0, s));
+    if ((rc = vcycle(p, l - 1, form, prec, Lc.w_x[prec], Lc.w_b[prec], s))) return rc;
+    ISS_HIP(k_prolong_add(L.v, Lc.v, prec, Lc.w_x[prec], x, s));
+    for (int i = 0; i < p->opt.nu2; ++i)
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, delta, s));
+    return ISS_OK;
+}
+
+int field_norms(iss_problem* p, int prec, const void* x, int64_t N, int nf, double* out, hipStream_t s) {
+    ISS_HIP(k_field_sumsq(prec, x, N, nf, p->d_partial, p->d_red, s));
+    ISS_HIP(hipMemcpyAsync(p->h_pinned, p->d_red, nf * sizeof(double), hipMemcpyDeviceToHost, s));
+    ISS_HIP(hipStreamSynchronize(s));
+    for (int f = 0; f < nf; ++f) out[f] = p->h_pinned[f];
+    return ISS_OK;
+}
+
+double total_norm(const double* sq, int nf) {
+    double t = 0;
+    for (int f = 0; f < nf; ++f) t += sq[f];
+    return std::sqrt(t);
+}
+
+// z = M^{-1} v: one V-cycle from zero in precision prec (FP64 in, FP64 out)
+int precondition(iss_problem* p, int form, int prec, const double* v, double* z, hipStream_t s) {
+    const int l = p->levels;
+    const int64_t n = (int64_t)(p->dim + 1) * p->lv[l].v.N;
+    int rc;
+    if ((rc = ensure_work(p, l, prec))) return rc;
+    Level& L = p->lv[l];
+    if (prec == PREC_F64) {
+        ISS_HIP(k_fill(PREC_F64, z, n, 0.0, s));
+        return vcycle(p, l, form, PREC_F64, z, v, s);
+    }
+    ISS_HIP(k_convert(PREC_F64, v, PREC_F32, L.w_b[PREC_F32], n, s));
+    ISS_HIP(k_fill(PREC_F32, L.w_x[PREC_F32], n, 0.0, s));
+    if ((rc = vcycle(p, l, form, PREC_F32, L.w_x[PREC_F32], L.w_b[PREC_F32], s))) return rc;
+    ISS_HIP(k_convert(PREC_F32, L.w_x[PREC_F32], PREC_F64, z, n, s));
+    return ISS_OK;
+}
+
+int ensure_krylov(iss_problem* p, int m) {
+    if (p->kry_m >= m && p->d_V) return ISS_OK;
+    if (2 * m + 4 > 8192) return fail(ISS_E_INVAL, "restart length too large");
+    if (p->d_V) {
+        (void)hipFree(p->d_V); (void)hipFree(p->d_Z); (void)hipFree(p->d_w); (void)hipFree(p->d_r); (void)hipFree(p->d_h);
+        auto rm = [&](void* q) { p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), q), p->allocs.end()); };
+        rm(p->d_V); rm(p->d_Z); rm(p->d_w); rm(p->d_r); rm(p->d_h);
+    }
+    const int64_t n = (int64_t)(p->dim + 1) * p->lv[p->levels].v.N;
+    int rc;
+    if ((rc = dev_alloc(p, (void**)&p->d_V, (size_t)(m + 1) * n * 8))) return rc;
+    if ((rc = dev_alloc(p, (void**)&p->d_Z, (size_t)m * n * 8))) return rc;
+    if ((rc = dev_alloc(p, (void**)&p->d_w, (size_t)n * 8))) return rc;
+    if ((rc = dev_alloc(p, (void**)&p->d_r, (size_t)n * 8))) return rc;
+    if ((rc = dev_alloc(p, (void**)&p->d_h, (size_t)(2 * m + 4) * 8))) return rc;
+    p->kry_m = m;
+    return ISS_OK;
+}
+
+int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x, const double* b,
+          iss_solve_info* info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int l = p->levels;
+    Level& L = p->lv[l];
+    const int D = p->dim;
+    const int64_t N = L.v.N, n = (int64_t)(D + 1) * N;
+    const int m = std::max(1, p->opt.restart);
+    int rc;
+    if ((rc = ensure_krylov(p, m))) return rc;
+    if ((rc = ensure_coarse(p, form))) return rc;
+    double sq[4];
+    if ((rc = field_norms(p, PREC_F64, b, N, D + 1, sq, s))) return rc;
+    const double nb = total_norm(sq, D + 1);
+    std::vector<double> hist;
+    int its = 0;
+    double rel = 0;
+    if (nb == 0.0) {
+        ISS_HIP(k_fill(PREC_F64, x, n, 0.0, s));
+        hist.push_back(0.0);
+    } else {
+        double* r = p->d_r;
+        ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, PREC_F64, x, b, r, s));
+        if ((rc = field_norms(p, PREC_F64, r, N, D + 1, sq, s))) return rc;
+        double beta = total_norm(sq, D + 1);
+        rel = beta / nb;
+        hist.push_back(rel);
+        const double rel0 = rel;
+        auto bad = [&](double v) { return !std::isfinite(v) || v > 1e3 * std::max(rel0, 1e-300); };
+        if (p->opt.outer == ISS_OUTER_RICHARDSON) {
+            while (rel > rtol && its < maxit) {
+                if ((rc = precondition(p, form, prec, r, p->d_w, s))) return rc;
+                ISS_HIP(k_axpby(x, 1.0, p->d_w, 1.0, n, s));
+                ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, PREC_F64, x, b, r, s));
+                if ((rc = field_norms(p, PREC_F64, r, N, D + 1, sq, s))) return rc;
+                rel = total_norm(sq, D + 1) / nb;
+                ++its;
+                hist.push_back(rel);
+                if (bad(rel)) { rc = ISS_E_DIVERGED; break; }
+            }
+        } else {
+            // right-preconditioned FGMRES(m), classical Gram-Schmidt applied twice
+            std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2);
+            double* V = p->d_V;
+            double* Z = p->d_Z;
+            double* w = p->d_w;
+            double* dh = p->d_h;
+            while (rel > rtol && its < maxit && rc == ISS_OK) {
+                // V_0 = r / beta
+                ISS_HIP(k_scale(V, 1.0 / beta, r, n, s));
+                std::fill(H.begin(), H.end(), 0.0);
+                std::fill(g.begin(), g.end(), 0.0);
+                g[0] = beta;
+                int j = 0;
+                for (; j < m && its < maxit; ++j) {
+                    if ((rc = precondition(p, form, prec, V + (size_t)j * n, Z + (size_t)j * n, s))) return rc;
+                    ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_APPLY, PREC_F64, Z + (size_t)j * n, nullptr, w, s));
+                    // h = V^T w ; w -= V h ; twice
+                    for (int pass = 0; pass < 2; ++pass) {
+                        double* hp = dh + (pass == 0 ? 0 : (m + 2));
+                        ISS_HIP(k_multidot(V, n, j + 1, w, n, p->d_partial, hp, s));
+                        ISS_HIP(k_multiaxpy(w, V, n, j + 1, hp, -1.0, n, s));
+                    }
+                    ISS_HIP(k_field_sumsq(PREC_F64, w, n, 1, p->d_partial, dh + (2 * m + 3), s));
+                    double* hh = p->h_pinned;
+                    ISS_HIP(hipMemcpyAsync(hh, dh, (2 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+                    ISS_HIP(hipStreamSynchronize(s));
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[m + 2 + i];
+                    const double hn = std::sqrt(hh[2 * m + 3]);
+                    H[(size_t)(j + 1) * m + j] = hn;
+                    if (hn > 0) ISS_HIP(k_scale(V + (size_t)(j + 1) * n, 1.0 / hn, w, n, s));
+                    for (int i = 0; i < j; ++i) {
+                        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+                    }
+                    const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+                    const double den = std::hypot(a, c);
+                    cs[j] = a / den;
+                    sn[j] = c / den;
+                    H[(size_t)j * m + j] = den;
+                    H[(size_t)(j + 1) * m + j] = 0.0;
+                    g[j + 1] = -sn[j] * g[j];
+                    g[j] = cs[j] * g[j];
+                    ++its;
+                    rel = std::fabs(g[j + 1]) / nb;
+                    hist.push_back(rel);
+                    if (!std::isfinite(rel)) { rc = ISS_E_DIVERGED; break; }
+                    if (rel <= rtol || hn == 0.0) { ++j; break; }
+                }
+                if (rc != ISS_OK) break;
+                // y = H^{-1} g ; x += Z y
+                std::vector<double> y(j);
+                for (int i = j - 1; i >= 0; --i) {
+                    double t = g[i];
+                    for (int k = i + 1; k < j; ++k) t -= H[(size_t)i * m + k] * y[k];
+                    y[i] = t / H[(size_t)i * m + i];
+                }
+                std::copy(y.begin(), y.end(), p->h_pinned);
+                ISS_HIP(hipMemcpyAsync(dh, p->h_pinned, j * sizeof(double), hipMemcpyHostToDevice, s));
+                ISS_HIP(k_multiaxpy(x, Z, n, j, dh, 1.0, n, s));
+                ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, PREC_F64, x, b, r, s));
+                if ((rc = field_norms(p, PREC_F64, r, N, D + 1, sq, s))) return rc;
+                beta = total_norm(sq, D + 1);
+                rel = beta / nb;
+                hist.back() = rel;
+                if (bad(rel)) { rc = ISS_E_DIVERGED; break; }
+            }
+        }
+    }
+    ISS_HIP(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+        info->iterations = its;
+        info->relres = rel;
+        info->seconds = secs;
+        const int cap = maxit + 1;
+        const int cnt = std::min<int>((int)hist.size(), cap);
+        info->history_len = info->history ? cnt : 0;
+        if (info->history)
+            for (int i = 0; i < cnt; ++i) info->history[i] = hist[i];
+    }
+    if (rc == ISS_E_DIVERGED) return fail(ISS_E_DIVERGED, "solve diverged (residual grew > 1e3 or not finite)");
+    if (rc != ISS_OK) return rc;
+    if (rel > rtol) return fail(ISS_E_NOTCONV, "maxit reached before tolerance");
+    return ISS_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+
+extern "C" {
+
+const char* iss_last_error(void) { return g_err.c_str(); }
+
+int iss_default_options(iss_options* o) {
+    if (!o) return fail(ISS_E_INVAL, "null options");
+    o->nu1 = 3;
+    o->nu2 = 3;
+    o->omega = 0.3;
+    o->stab_beta = 1.0 / 12.0;
+    o->outer = ISS_OUTER_RICHARDSON;
+    o->restart = 40;
+    return ISS_OK;
+}
+
+void iss_problem_destroy(iss_problem* p) {
+    if (!p) return;
+    for (void* q : p->allocs) (void)hipFree(q);
+    if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+    delete p;
+}
+
+int iss_problem_create(int dim, int macro, int levels, int coarse_level,
+                       const iss_inclusion* inclusions, int ninclusions, const double* mu, int nphase,
+                       const iss_options* opt, iss_problem** out) {
+    if (!out) return fail(ISS_E_INVAL, "null out");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(ISS_E_INVAL, "dim must be 2 or 3");
+    if (macro < 1 || levels < 1 || coarse_level < 1 || coarse_level > levels)
+        return fail(ISS_E_INVAL, "need macro >= 1 and 1 <= coarse_level <= levels");
+    const int64_t n = (int64_t)macro << levels;
+    const int64_t N = (dim == 3) ? (n + 1) * (n + 1) * (n + 1) : (n + 1) * (n + 1);
+    if ((int64_t)(dim + 1) * N >= (int64_t)1 << 31) return fail(ISS_E_INVAL, "problem too large for int32 indices");
+    if (!mu || nphase < 1 || nphase > 254) return fail(ISS_E_INVAL, "need 1 <= nphase <= 254");
+    for (int i = 0; i < nphase; ++i)
+        if (!(mu[i] > 0) || !std::isfinite(mu[i])) return fail(ISS_E_INVAL, "viscosities must be positive and finite");
+    if (ninclusions < 0 || (ninclusions > 0 && !inclusions)) return fail(ISS_E_INVAL, "bad inclusions");
+    for (int i = 0; i < ninclusions; ++i) {
+        const auto& in = inclusions[i];
+        if (in.phase < 0 || in.phase >= nphase) return fail(ISS_E_INVAL, "inclusion phase out of range");
+        if (in.kind != ISS_SPHERE && in.kind != ISS_HALFSPACE) return fail(ISS_E_INVAL, "bad inclusion kind");
+        if (in.kind == ISS_HALFSPACE && (in.a[0] < 0 || (int)in.a[0] >= dim))
+            return fail(ISS_E_INVAL, "half-space axis out of range");
+    }
+    iss_problem* p = new (std::nothrow) iss_problem();
+    if (!p) return fail(ISS_E_NOMEM, "host allocation failed");
+    p->dim = dim;
+    p->macro = macro;
+    p->levels = levels;
+    p->coarse = coarse_level;
+    p->inc.assign(inclusions, inclusions + ninclusions);
+    p->mu.assign(mu, mu + nphase);
+    p->mu.resize(256, 1.0);
+    if (opt) p->opt = *opt;
+    else iss_default_options(&p->opt);
+    if (p->opt.nu1 < 0 || p->opt.nu2 < 0 || !(p->opt.stab_beta > 0) || p->opt.restart < 1 ||
+        (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES)) {
+        delete p;
+        return fail(ISS_E_INVAL, "bad options");
+    }
+    int rc = ISS_OK;
+    do {
+        std::vector<double> imu(256);
+        std::vector<float> mu32(256), imu32(256);
+        for (int i = 0; i < 256; ++i) {
+            imu[i] = 1.0 / p->mu[i];
+            mu32[i] = (float)p->mu[i];
+            imu32[i] = (float)imu[i];
+        }
+        if ((rc = dev_upload(p, &p->d_mu64, p->mu.data(), 256))) break;
+        if ((rc = dev_upload(p, &p->d_imu64, imu.data(), 256))) break;
+        if ((rc = dev_upload(p, &p->d_mu32, mu32.data(), 256))) break;
+        if ((rc = dev_upload(p, &p->d_imu32, imu32.data(), 256))) break;
+        if ((rc = dev_alloc(p, (void**)&p->d_partial, 1024 * 64 * sizeof(double)))) break;
+        if ((rc = dev_alloc(p, (void**)&p->d_red, 64 * sizeof(double)))) break;
+        if ((rc = dev_alloc(p, (void**)&p->d_flag, 256))) break;
+        if (hipHostMalloc((void**)&p->h_pinned, 8192 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            rc = fail(ISS_E_NOMEM, "pinned host allocation failed");
+            break;
+        }
+        if (dim == 3) {
+            if ((rc = build_tables<3>(p->t3))) break;
+            ElemTables<3, float> f;
+            to_float<3>(p->t3, f);
+            hipError_t e = upload_tables(3, &p->t3, sizeof(p->t3), &f, sizeof(f));
+            if (e != hipSuccess) { rc = fail(ISS_E_HIP, std::string("upload tables: ") + hipGetErrorString(e)); break; }
+        } else {
+            if ((rc = build_tables<2>(p->t2))) break;
+            ElemTables<2, float> f;
+            to_float<2>(p->t2, f);
+            hipError_t e = upload_tables(2, &p->t2, sizeof(p->t2), &f, sizeof(f));
+            if (e != hipSuccess) { rc = fail(ISS_E_HIP, std::string("upload tables: ") + hipGetErrorString(e)); break; }
+        }
+        p->lv.resize(levels + 1);
+        for (int l = coarse_level; l <= levels && rc == ISS_OK; ++l)
+            rc = (dim == 3) ? setup_level<3>(p, l) : setup_level<2>(p, l);
+        if (rc) break;
+        // keep element phases only where the coarse matrix needs them
+        for (int l = coarse_level + 1; l <= levels; ++l) std::vector<uint8_t>().swap(p->lv[l].elem_phase);
+    } while (0);
+    if (rc) {
+        iss_problem_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return ISS_OK;
+}
+
+int iss_num_vertices(const iss_problem* p, int level, int64_t* n) {
+    if (!p || !n) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_level(p, level))) return rc;
+    *n = p->lv[level].v.N;
+    return ISS_OK;
+}
+
+int iss_vertex_class(const iss_problem* p, int level, uint8_t* cls, int64_t* ninterface,
+                     int64_t* nboundary) {
+    if (!p) return fail(ISS_E_INVAL, "null problem");
+    int rc;
+    if ((rc = check_level(p, level))) return rc;
+    const Level& L = p->lv[level];
+    if (cls) std::memcpy(cls, L.cls.data(), L.cls.size());
+    if (ninterface) *ninterface = L.ninterface;
+    if (nboundary) *nboundary = L.nboundary;
+    return ISS_OK;
+}
+
+int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant, double rho,
+                     double* b, iss_stream_t stream) {
+    if (!p || !b || (nbuoyant > 0 && !phases)) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_level(p, level))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t flag[256] = {0};
+    for (int i = 0; i < nbuoyant; ++i) {
+        if (phases[i] < 0 || phases[i] > 253) return fail(ISS_E_INVAL, "bad buoyant phase");
+        flag[phases[i]] = 1;
+    }
+    ISS_HIP(hipStreamSynchronize(s));
+    ISS_HIP(hipMemcpy(p->d_flag, flag, 256, hipMemcpyHostToDevice));
+    const Level& L = p->lv[level];
+    ISS_HIP(k_fill(PREC_F64, b, (int64_t)(p->dim + 1) * L.v.N, 0.0, s));
+    double vol = 1.0;
+    for (int a = 0; a < p->dim; ++a) vol /= L.v.n;
+    vol /= (p->dim == 3 ? 6.0 : 2.0);
+    ISS_HIP(k_rhs_buoyancy(L.v, p->d_flag, rho, vol, b, s));
+    ISS_HIP(hipStreamSynchronize(s));   // flag buffer is reused by the next call
+    return ISS_OK;
+}
+
+int iss_apply(iss_problem* p, int form, int block, int level, int prec, const void* x, void* y,
+              iss_stream_t stream) {
+    if (!p || !x || !y) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    if (block != ISS_VELOCITY_ONLY && block != ISS_FULL_STOKES) return fail(ISS_E_INVAL, "bad block");
+    ISS_HIP(k_apply(p->lv[level].v, form, block, MODE_APPLY, prec, x, nullptr, y, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_residual(iss_problem* p, int form, int level, int prec, const void* x, const void* b, void* r,
+                 double* norms, iss_stream_t stream) {
+    if (!p || !x || !b || !r) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Level& L = p->lv[level];
+    ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, r, s));
+    if (norms) {
+        double sq[4];
+        if ((rc = field_norms(p, prec, r, L.v.N, p->dim + 1, sq, s))) return rc;
+        for (int f = 0; f <= p->dim; ++f) norms[f] = std::sqrt(sq[f]);
+        norms[p->dim + 1] = total_norm(sq, p->dim + 1);
+    }
+    return ISS_OK;
+}
+
+int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps, void* x, const void* b,
+               iss_stream_t stream) {
+    if (!p || !x || !b || nsteps < 0) return fail(ISS_E_INVAL, "bad argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    if ((rc = ensure_work(p, level, prec))) return rc;
+    Level& L = p->lv[level];
+    const size_t es = prec == PREC_F64 ? 8 : 4;
+    void* delta = (char*)L.w_r[prec] + (size_t)p->dim * L.v.N * es;
+    for (int i = 0; i < nsteps; ++i)
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, delta, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_restrict(iss_problem* p, int level, int prec, const void* rf, void* rc_, iss_stream_t stream) {
+    if (!p || !rf || !rc_) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    if (level == p->coarse) return fail(ISS_E_INVAL, "no coarser level");
+    ISS_HIP(k_restrict(p->lv[level].v, p->lv[level - 1].v, prec, rf, rc_, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_prolong_add(iss_problem* p, int level, int prec, const void* ec, void* xf, iss_stream_t stream) {
+    if (!p || !ec || !xf) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    if (level == p->coarse) return fail(ISS_E_INVAL, "no coarser level");
+    ISS_HIP(k_prolong_add(p->lv[level].v, p->lv[level - 1].v, prec, ec, xf, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_coarse_solve(iss_problem* p, int form, const double* b, double* x, iss_stream_t stream) {
+    if (!p || !b || !x) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_form(form))) return rc;
+    return coarse_solve(p, form, PREC_F64, b, x, (hipStream_t)stream);
+}
+
+int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b, iss_stream_t stream) {
+    if (!p || !x || !b) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec))) return rc;
+    return vcycle(p, p->levels, form, prec, x, b, (hipStream_t)stream);
+}
+
+int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x, const double* b,
+              iss_solve_info* info, iss_stream_t stream) {
+    if (!p || !x || !b) return fail(ISS_E_INVAL, "null argument");
+    if (!(rtol > 0) || maxit < 0) return fail(ISS_E_INVAL, "need rtol > 0 and maxit >= 0");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec))) return rc;
+    return solve(p, form, prec, rtol, maxit, x, b, info, (hipStream_t)stream);
+}
+
+int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double* out, iss_stream_t stream) {
+    if (!p || !a || !b || !out || n < 0) return fail(ISS_E_INVAL, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    ISS_HIP(k_multidot(a, 0, 1, b, n, p->d_partial, p->d_red, s));
+    ISS_HIP(hipMemcpyAsync(p->h_pinned, p->d_red, sizeof(double), hipMemcpyDeviceToHost, s));
+    ISS_HIP(hipStreamSynchronize(s));
+    *out = p->h_pinned[0];
+    return ISS_OK;
+}
+
+}  // extern "C"

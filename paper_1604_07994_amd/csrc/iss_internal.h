@@ -1,0 +1,75 @@
+// Internal declarations shared by the host setup/solver code and the HIP
+// kernels of the Stokes hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "iss_geometry.h"
+
+namespace iss {
+
+constexpr uint8_t SPECIAL = 255;   // vertex phase byte: needs the element loop
+constexpr uint8_t OUTSIDE = 255;   // incident-element phase: outside the domain
+
+enum { FORM_GRADIENT = 0, FORM_STRAIN = 1, FORM_INTERFACE = 2 };
+enum { BLOCK_VEL = 0, BLOCK_FULL = 1 };
+enum { MODE_APPLY = 0, MODE_RESID = 1 };
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+
+// Per-level data as seen by the kernels (all pointers are device pointers).
+struct LevelView {
+    int dim;
+    int n;                   // cells per axis; vertices 0..n per axis
+    int64_t N;               // (n+1)^dim
+    int64_t sy, sz;          // strides of j and k (sz = 0 in 2D)
+    const uint8_t* vphase;   // per vertex: phase, or SPECIAL
+    const int32_t* spec;     // special vertices grouped by colour
+    const uint8_t* spec_eph; // per special vertex: phase of each slot
+    int64_t spec_off[5];     // colour c occupies [spec_off[c], spec_off[c+1])
+    const double* mu64;      // viscosity per phase
+    const double* imu64;     // 1 / viscosity per phase
+    const float* mu32;
+    const float* imu32;
+    double sA, sB, sC;       // h^(d-2), h^(d-1), beta h^d
+};
+
+// Kernel launchers (iss_kernels.hip).  `prec` selects double / float
+// vectors.  Each returns hipSuccess or the launch error.
+hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t32,
+                         size_t bytes32);
+hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec,
+                   const void* x, const void* b, void* y, hipStream_t s);
+hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* x,
+                         const void* b, void* delta, hipStream_t s);
+hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf,
+                      void* rc, hipStream_t s);
+hipError_t k_prolong_add(const LevelView& Lf, const LevelView& Lc, int prec, const void* ec,
+                         void* xf, hipStream_t s);
+hipError_t k_fill(int prec, void* x, int64_t n, double value, hipStream_t s);
+hipError_t k_convert(int prec_in, const void* in, int prec_out, void* out, int64_t n,
+                     hipStream_t s);
+// sums of squares per field (nf fields of length N) -> out[0..nf-1] (device,
+// FP64), using `partial` (device, >= 1024 * nf doubles) as scratch.
+hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* partial,
+                         double* out, hipStream_t s);
+// out[i] = sum_e V_i[e] w[e] for i < k (V_i = V + i * ldv); partial >= 512 * k
+hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                      double* partial, double* out, hipStream_t s);
+// y += alpha * sum_i c[i] X_i  (c on device)
+hipError_t k_multiaxpy(double* y, const double* X, int64_t ldx, int k, const double* c,
+                       double alpha, int64_t n, hipStream_t s);
+// y = a * x
+hipError_t k_scale(double* y, double a, const double* x, int64_t n, hipStream_t s);
+hipError_t k_axpby(double* y, double a, const double* x, double b, int64_t n,
+                   hipStream_t s);
+hipError_t k_gather(int prec, const void* x, const int32_t* idx, int64_t m, double* out,
+                    hipStream_t s);
+hipError_t k_scatter(int prec, const double* in, const int32_t* idx, int64_t m, void* x,
+                     hipStream_t s);
+hipError_t k_dense_matvec(const double* A, int64_t m, const double* x, double* y,
+                          hipStream_t s);
+hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* buoyant_flag, double rho,
+                          double vol_unit, double* b, hipStream_t s);
+
+}  // namespace iss

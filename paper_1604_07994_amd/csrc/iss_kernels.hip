@@ -1,0 +1,958 @@
+// HIP kernels (gfx950) of the matrix-free Stokes hot path.
+//
+// Operators (Sec. 5 saddle point system K = [[A, B^T], [B, -C]]):
+//   * bulk kernels handle interior vertices whose incident elements share
+//     one viscosity: constant stencils scaled by that viscosity -- for the
+//     gradient and interface forms the decoupled Laplacian stencil per
+//     velocity component (eq. equivalence-stencil, Sec. 2.2), for the
+//     strain form the coupled 3x3-block stencil (eq. standard);
+//   * special kernels handle the compact list of interface and boundary
+//     vertices by looping over the incident elements with their own
+//     viscosities (the full a_tr / a_sym rows of Sec. 2.2; truncated
+//     pressure rows on the boundary).
+// The smoother is the Uzawa step of eq. Uzawa_smooth with multicolour
+// Gauss-Seidel sweeps; colour (i + j + k) mod (d + 1).  No MFMA: every
+// kernel here is bound by HBM traffic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "iss_internal.h"
+
+namespace iss {
+
+__constant__ ElemTables<3, double> g_e3d;
+__constant__ ElemTables<3, float> g_e3f;
+__constant__ ElemTables<2, double> g_e2d;
+__constant__ ElemTables<2, float> g_e2f;
+
+template <int D, typename C> struct ETab;
+template <> struct ETab<3, double> { __device__ static const ElemTables<3, double>& get() { return g_e3d; } };
+template <> struct ETab<3, float> { __device__ static const ElemTables<3, float>& get() { return g_e3f; } };
+template <> struct ETab<2, double> { __device__ static const ElemTables<2, double>& get() { return g_e2d; } };
+template <> struct ETab<2, float> { __device__ static const ElemTables<2, float>& get() { return g_e2f; } };
+
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+    __device__ static double mu(const LevelView& L, int ph) { return L.mu64[ph]; }
+    __device__ static double imu(const LevelView& L, int ph) { return L.imu64[ph]; }
+};
+template <> struct Prec<float> {
+    __device__ static float mu(const LevelView& L, int ph) { return L.mu32[ph]; }
+    __device__ static float imu(const LevelView& L, int ph) { return L.imu32[ph]; }
+};
+
+// ----------------------------------------------------------------------------
+// thread -> vertex maps
+
+// Spread consecutive workgroups over the 8 XCDs in contiguous chunks: the
+// dispatcher sends workgroup b to XCD b % 8, so remapping makes every XCD
+// walk one contiguous slab of the lattice and keeps stencil halos in its
+// own L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, idx = b >> 3;
+    const int64_t per = nb >> 3, rem = nb & 7;
+    return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+constexpr int BX = 64, BY = 4;   // 256-thread workgroups: 64 along x, 4 rows
+
+// Interior vertex (1..n-1 per axis) of a bulk kernel; `step` > 1 walks one
+// colour class along x.  Returns false for threads past the row end.
+template <int D>
+__device__ __forceinline__ bool interior_vertex(const LevelView& L, int colour, int step,
+                                                int& i, int& j, int& k) {
+    const int m = L.n - 1;                       // interior points per axis
+    const int cnt = (step == 1) ? m : (m + step - 1) / step;
+    const int gx = (cnt + BX - 1) / BX, gy = (m + BY - 1) / BY;
+    const int64_t nb = (int64_t)gx * gy * (D == 3 ? m : 1);
+    const int64_t b = xcd_remap(blockIdx.x, nb);
+    const int bx = (int)(b % gx);
+    const int64_t r = b / gx;
+    const int by = (int)(r % gy);
+    k = (D == 3) ? 1 + (int)(r / gy) : 0;
+    j = 1 + by * BY + (int)threadIdx.y;
+    if (j > m) return false;
+    const int t = bx * BX + (int)threadIdx.x;
+    if (step == 1) {
+        i = 1 + t;
+    } else {
+        int i0 = (colour - j - k) % step;
+        if (i0 < 0) i0 += step;
+        if (i0 == 0) i0 = step;                   // first i >= 1 in the class
+        i = i0 + step * t;
+    }
+    return i <= m;
+}
+
+template <int D>
+inline int64_t interior_blocks(int n, int step) {
+    const int m = n - 1;
+    if (m <= 0) return 0;
+    const int cnt = (step == 1) ? m : (m + step - 1) / step;
+    return (int64_t)((cnt + BX - 1) / BX) * ((m + BY - 1) / BY) * (D == 3 ? m : 1);
+}
+
+template <int D>
+__device__ __forceinline__ int64_t nb_lin(const LevelView& L, int o) {
+    constexpr auto& T = Kuhn<D>::T;
+    return (int64_t)T.off[o][0] + (int64_t)T.off[o][1] * L.sy + (int64_t)T.off[o][2] * L.sz;
+}
+
+// ----------------------------------------------------------------------------
+// neighbourhood loads
+
+template <int D, int NF, typename T, typename C>
+__device__ __forceinline__ void load_interior(const LevelView& L, const T* __restrict__ x,
+                                              int64_t v, int f0, C (&V)[NF][KuhnTables<D>::NB]) {
+    constexpr int NB = KuhnTables<D>::NB;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int o = 0; o < NB; ++o)
+            V[f][o] = (C)x[(int64_t)(f0 + f) * L.N + v + nb_lin<D>(L, o)];
+}
+
+// guarded load for vertices that may sit on the boundary
+template <int D, int NF, typename T, typename C>
+__device__ __forceinline__ void load_guarded(const LevelView& L, const T* __restrict__ x,
+                                             int64_t v, const int (&ijk)[3], int f0,
+                                             C (&V)[NF][KuhnTables<D>::NB]) {
+    constexpr auto& TT = Kuhn<D>::T;
+    constexpr int NB = KuhnTables<D>::NB;
+#pragma unroll
+    for (int o = 0; o < NB; ++o) {
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int c = ijk[a] + TT.off[o][a];
+            in = in && (c >= 0) && (c <= L.n);
+        }
+        const int64_t nv = v + nb_lin<D>(L, o);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            V[f][o] = in ? (C)x[(int64_t)(f0 + f) * L.N + nv] : (C)0;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void vertex_ijk(const LevelView& L, int64_t v, int (&ijk)[3]) {
+    const int64_t n1 = L.n + 1;
+    ijk[0] = (int)(v % n1);
+    const int64_t r = v / n1;
+    ijk[1] = (int)(r % n1);
+    ijk[2] = (D == 3) ? (int)(r / n1) : 0;
+}
+
+template <int D>
+__device__ __forceinline__ bool on_boundary(const LevelView& L, const int (&ijk)[3]) {
+    bool b = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) b = b || ijk[a] == 0 || ijk[a] == L.n;
+    return b;
+}
+
+// ----------------------------------------------------------------------------
+// element loop of one special vertex: rows of A (form F), B^T, B and C.
+
+template <int D, int F, bool VEL, bool PRES, typename C>
+struct RowAcc {
+    C au[D];          // sum_T mu_T A_T u          (unscaled by sA)
+    C abt[D];         // sum_T B_T^T p             (unscaled by sB)
+    C Dm[D][D];       // point diagonal block of sum_T mu_T A_T
+    C bdiv;           // sum_T B_T u
+    C cp;             // sum_T (1/mu_T) C_T p      (unscaled by sC)
+    C cd;             // sum_T (1/mu_T) C_T delta
+    C cjj;            // point diagonal of sum_T (1/mu_T) C_T
+};
+
+template <int D, int F, bool VEL, bool PRES, bool WANT_D, bool WANT_DELTA, typename T, typename C>
+__device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
+                                             const C (&U)[D][KuhnTables<D>::NB],
+                                             const C (&P)[KuhnTables<D>::NB],
+                                             const C (&Dl)[KuhnTables<D>::NB],
+                                             RowAcc<D, F, VEL, PRES, C>& r) {
+    constexpr auto& TT = Kuhn<D>::T;
+    constexpr int NS = KuhnTables<D>::NS;
+    const auto& E = ETab<D, C>::get();
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        r.au[a] = 0; r.abt[a] = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) r.Dm[a][b] = 0;
+    }
+    r.bdiv = 0; r.cp = 0; r.cd = 0; r.cjj = 0;
+    const uint8_t* eph = L.spec_eph + s * NS;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+        const int ph = eph[sl];
+        if (ph == OUTSIDE) continue;
+        constexpr int dummy = 0; (void)dummy;
+        const int ty = TT.slot_type[sl];
+        const int a = TT.slot_loc[sl];
+        const C mu = Prec<C>::mu(L, ph);
+        const C imu = Prec<C>::imu(L, ph);
+#pragma unroll
+        for (int bb = 0; bb <= D; ++bb) {
+            const int o = TT.slot_nb[sl][bb];
+            if (VEL) {
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    C acc = 0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) acc += E.Avis[F][ty][a * D + l][bb * D + k] * U[k][o];
+                    r.au[l] += mu * acc;
+                    r.abt[l] += E.Bel[ty][bb][a * D + l] * P[o];
+                }
+                if (WANT_D && bb == a) {
+#pragma unroll
+                    for (int l = 0; l < D; ++l)
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+                            r.Dm[l][k] += mu * E.Avis[F][ty][a * D + l][a * D + k];
+                }
+            }
+            if (PRES) {
+                C acc = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) acc += E.Bel[ty][a][bb * D + k] * U[k][o];
+                r.bdiv += acc;
+                r.cp += imu * E.Cel[ty][a][bb] * P[o];
+                if (WANT_DELTA) r.cd += imu * E.Cel[ty][a][bb] * Dl[o];
+                if (WANT_D && bb == a) r.cjj += imu * E.Cel[ty][a][a];
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// operator apply / residual
+
+template <int D, int F, int BLK, int MODE, typename T>
+__global__ __launch_bounds__(256) void k_apply_bulk(LevelView L, const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    int i, j, k;
+    if (!interior_vertex<D>(L, 0, 1, i, j, k)) return;
+    const int64_t v = i + j * L.sy + k * L.sz;
+    const int ph = L.vphase[v];
+    if (ph == SPECIAL) return;
+    const auto& E = ETab<D, C>::get();
+    const C mu = Prec<C>::mu(L, ph);
+    const C smu = mu * (C)L.sA;
+    C out[D + 1];
+    if (BLK == BLOCK_FULL || F == FORM_STRAIN) {
+        C U[D][NB];
+        load_interior<D, D, T, C>(L, x, v, 0, U);
+        if (F == FORM_STRAIN) {
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                C acc = 0;
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+                    for (int o = 0; o < NB; ++o) acc += E.Svis[1][l][kk][o] * U[kk][o];
+                out[l] = smu * acc;
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                C acc = E.Svis[0][l][l][0] * U[l][0];
+#pragma unroll
+                for (int o = 1; o <= 2 * D; ++o) acc += E.Svis[0][l][l][o] * U[l][o];
+                out[l] = smu * acc;
+            }
+        }
+        if (BLK == BLOCK_FULL) {
+            C P[1][NB];
+            load_interior<D, 1, T, C>(L, x, v, D, P);
+            const C sB = (C)L.sB;
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                C acc = 0;
+#pragma unroll
+                for (int o = 1; o < NB; ++o) acc += E.Sbt[l][o] * P[0][o];
+                out[l] += sB * acc;
+            }
+            C dv = 0;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+                for (int o = 1; o < NB; ++o) dv += E.Sdiv[kk][o] * U[kk][o];
+            C cp = E.Sc[0] * P[0][0];
+#pragma unroll
+            for (int o = 1; o <= 2 * D; ++o) cp += E.Sc[o] * P[0][o];
+            out[D] = sB * dv - (C)L.sC * Prec<C>::imu(L, ph) * cp;
+        } else {
+            out[D] = 0;
+        }
+    } else {
+        // decoupled Laplacian rows: only the axis neighbours of each component
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            const T* ul = x + (int64_t)l * L.N + v;
+            C acc = E.Svis[0][l][l][0] * (C)ul[0];
+#pragma unroll
+            for (int o = 1; o <= 2 * D; ++o) acc += E.Svis[0][l][l][o] * (C)ul[nb_lin<D>(L, o)];
+            out[l] = smu * acc;
+        }
+        out[D] = 0;
+    }
+#pragma unroll
+    for (int f = 0; f <= D; ++f) {
+        const int64_t e = (int64_t)f * L.N + v;
+        if (MODE == MODE_RESID)
+            y[e] = (BLK == BLOCK_FULL || f < D) ? (T)(b[e] - out[f]) : (T)0;
+        else
+            y[e] = (T)out[f];
+    }
+}
+
+template <int D, int F, int BLK, int MODE, typename T>
+__global__ __launch_bounds__(256) void k_apply_special(LevelView L, const T* __restrict__ x,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ y) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= L.spec_off[D + 1]) return;
+    const int64_t v = L.spec[s];
+    int ijk[3];
+    vertex_ijk<D>(L, v, ijk);
+    const bool bnd = on_boundary<D>(L, ijk);
+    C U[D][NB], P[1][NB], Dl[NB];
+    load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
+    load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
+    RowAcc<D, F, true, BLK == BLOCK_FULL, C> r;
+    element_rows<D, F, true, BLK == BLOCK_FULL, false, false, T, C>(L, s, U, P[0], Dl, r);
+    C out[D + 1];
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+        out[l] = bnd ? (C)0 : (C)L.sA * r.au[l] + (BLK == BLOCK_FULL ? (C)L.sB * r.abt[l] : (C)0);
+    out[D] = (BLK == BLOCK_FULL) ? (C)L.sB * r.bdiv - (C)L.sC * r.cp : (C)0;
+#pragma unroll
+    for (int f = 0; f <= D; ++f) {
+        const int64_t e = (int64_t)f * L.N + v;
+        if (MODE == MODE_RESID) {
+            const bool zero = (f < D && bnd) || (f == D && BLK != BLOCK_FULL);
+            y[e] = zero ? (T)0 : (T)(b[e] - out[f]);
+        } else {
+            y[e] = (T)out[f];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Uzawa smoother pieces
+
+// velocity: one colour phase of the symmetric Gauss-Seidel sweep on
+// A u = f - B^T p.  BWD selects the reversed component order.
+template <int D, int F, bool BWD, typename C>
+__device__ __forceinline__ void block_gs_update(C (&r)[D], const C (&Dm)[D][D], C (&du)[D]) {
+    if (!BWD) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            C rl = r[l];
+#pragma unroll
+            for (int k = 0; k < l; ++k) rl -= Dm[l][k] * du[k];
+            du[l] = rl / Dm[l][l];
+        }
+    } else {
+#pragma unroll
+        for (int l = D - 1; l >= 0; --l) {
+            C rl = r[l];
+#pragma unroll
+            for (int k = D - 1; k > l; --k) rl -= Dm[l][k] * du[k];
+            du[l] = rl / Dm[l][l];
+        }
+    }
+}
+
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_bulk(LevelView L, int colour, T* __restrict__ x,
+                                                     const T* __restrict__ b) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    int i, j, k;
+    if (!interior_vertex<D>(L, colour, D + 1, i, j, k)) return;
+    const int64_t v = i + j * L.sy + k * L.sz;
+    const int ph = L.vphase[v];
+    if (ph == SPECIAL) return;
+    const auto& E = ETab<D, C>::get();
+    const C smu = Prec<C>::mu(L, ph) * (C)L.sA;
+    C P[1][NB];
+    load_interior<D, 1, T, C>(L, x, v, D, P);
+    C rhs[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        C acc = 0;
+#pragma unroll
+        for (int o = 1; o < NB; ++o) acc += E.Sbt[l][o] * P[0][o];
+        rhs[l] = (C)b[(int64_t)l * L.N + v] - (C)L.sB * acc;
+    }
+    if (F == FORM_STRAIN) {
+        C U[D][NB];
+        load_interior<D, D, T, C>(L, x, v, 0, U);
+        C r[D], Dm[D][D], du[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            C acc = 0;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+#pragma unroll
+                for (int o = 0; o < NB; ++o) acc += E.Svis[1][l][kk][o] * U[kk][o];
+                Dm[l][kk] = smu * E.Svis[1][l][kk][0];
+            }
+            r[l] = rhs[l] - smu * acc;
+        }
+        block_gs_update<D, F, BWD, C>(r, Dm, du);
+#pragma unroll
+        for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)(U[l][0] + du[l]);
+    } else {
+        // decoupled components: u_l = (rhs_l / (mu sA) - sum_nb w u_l) / w_0
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            T* ul = x + (int64_t)l * L.N + v;
+            C acc = 0;
+#pragma unroll
+            for (int o = 1; o <= 2 * D; ++o) acc += E.Svis[0][l][l][o] * (C)ul[nb_lin<D>(L, o)];
+            const C w0 = smu * E.Svis[0][l][l][0];
+            ul[0] = (T)((rhs[l] - smu * acc) / w0);
+        }
+    }
+}
+
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_special(LevelView L, int colour,
+                                                        T* __restrict__ x,
+                                                        const T* __restrict__ b) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    const int64_t s = L.spec_off[colour] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= L.spec_off[colour + 1]) return;
+    const int64_t v = L.spec[s];
+    int ijk[3];
+    vertex_ijk<D>(L, v, ijk);
+    if (on_boundary<D>(L, ijk)) return;          // Dirichlet velocity
+    C U[D][NB], P[1][NB], Dl[NB];
+    load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
+    load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
+    RowAcc<D, F, true, false, C> r;
+    element_rows<D, F, true, false, true, false, T, C>(L, s, U, P[0], Dl, r);
+    C res[D], Dm[D][D], du[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        res[l] = (C)b[(int64_t)l * L.N + v] - (C)L.sB * r.abt[l] - (C)L.sA * r.au[l];
+#pragma unroll
+        for (int k = 0; k < D; ++k) Dm[l][k] = (C)L.sA * r.Dm[l][k];
+    }
+    block_gs_update<D, F, BWD, C>(res, Dm, du);
+#pragma unroll
+    for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)(U[l][0] + du[l]);
+}
+
+// pressure: one colour phase of the forward Gauss-Seidel sweep on
+// C delta = B u - C p - g started from delta = 0.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_bulk(LevelView L, int colour,
+                                                   const T* __restrict__ x,
+                                                   const T* __restrict__ b,
+                                                   T* __restrict__ delta) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    int i, j, k;
+    if (!interior_vertex<D>(L, colour, D + 1, i, j, k)) return;
+    const int64_t v = i + j * L.sy + k * L.sz;
+    const int ph = L.vphase[v];
+    if (ph == SPECIAL) return;
+    const auto& E = ETab<D, C>::get();
+    C U[D][NB], P[1][NB];
+    load_interior<D, D, T, C>(L, x, v, 0, U);
+    load_interior<D, 1, T, C>(L, x, v, D, P);
+    C dv = 0;
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+        for (int o = 1; o < NB; ++o) dv += E.Sdiv[kk][o] * U[kk][o];
+    const C sci = (C)L.sC * Prec<C>::imu(L, ph);
+    C cp = E.Sc[0] * P[0][0], cd = 0;
+#pragma unroll
+    for (int o = 1; o <= 2 * D; ++o) {
+        cp += E.Sc[o] * P[0][o];
+        cd += E.Sc[o] * (C)delta[v + nb_lin<D>(L, o)];
+    }
+    const C sres = (C)L.sB * dv - sci * cp - (C)b[(int64_t)D * L.N + v];
+    delta[v] = (T)((sres - sci * cd) / (sci * E.Sc[0]));
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_special(LevelView L, int colour,
+                                                      const T* __restrict__ x,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ delta) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    const int64_t s = L.spec_off[colour] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= L.spec_off[colour + 1]) return;
+    const int64_t v = L.spec[s];
+    int ijk[3];
+    vertex_ijk<D>(L, v, ijk);
+    C U[D][NB], P[1][NB], Dl[1][NB];
+    load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
+    load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
+    load_guarded<D, 1, T, C>(L, delta, v, ijk, 0, Dl);
+    RowAcc<D, FORM_GRADIENT, false, true, C> r;
+    element_rows<D, FORM_GRADIENT, false, true, true, true, T, C>(L, s, U, P[0], Dl[0], r);
+    const C sres = (C)L.sB * r.bdiv - (C)L.sC * r.cp - (C)b[(int64_t)D * L.N + v];
+    delta[v] = (T)((sres - (C)L.sC * r.cd) / ((C)L.sC * r.cjj));
+}
+
+template <typename T>
+__global__ void k_axpy_field(T* __restrict__ p, const T* __restrict__ d, T w, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] += w * d[e];
+}
+
+template <typename T>
+__global__ void k_fill_t(T* __restrict__ x, int64_t n, T val) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) x[e] = val;
+}
+
+// ----------------------------------------------------------------------------
+// transfers: P1 interpolation between nested Kuhn lattices.  A fine vertex
+// with even coordinates is a coarse vertex; otherwise it is the midpoint
+// of the coarse edge along its odd-coordinate pattern (a Kuhn direction).
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_restrict_t(LevelView Lf, LevelView Lc,
+                                                    const T* __restrict__ rf,
+                                                    T* __restrict__ rc) {
+    constexpr auto& TT = Kuhn<D>::T;
+    constexpr int NB = KuhnTables<D>::NB;
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= Lc.N) return;
+    int c[3];
+    vertex_ijk<D>(Lc, I, c);
+    const bool bnd = on_boundary<D>(Lc, c);
+    const int64_t F = 2 * c[0] + 2 * c[1] * Lf.sy + 2 * c[2] * Lf.sz;
+    T acc[D + 1];
+#pragma unroll
+    for (int f = 0; f <= D; ++f) acc[f] = rf[(int64_t)f * Lf.N + F];
+#pragma unroll
+    for (int o = 1; o < NB; ++o) {
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int q = 2 * c[a] + TT.off[o][a];
+            in = in && q >= 0 && q <= Lf.n;
+        }
+        if (!in) continue;
+        const int64_t fo = F + nb_lin<D>(Lf, o);
+#pragma unroll
+        for (int f = 0; f <= D; ++f) acc[f] += (T)0.5 * rf[(int64_t)f * Lf.N + fo];
+    }
+#pragma unroll
+    for (int f = 0; f <= D; ++f) rc[(int64_t)f * Lc.N + I] = (f < D && bnd) ? (T)0 : acc[f];
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_prolong_t(LevelView Lf, LevelView Lc,
+                                                   const T* __restrict__ ec,
+                                                   T* __restrict__ xf) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Lf.N) return;
+    int a[3];
+    vertex_ijk<D>(Lf, v, a);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    bool odd = false;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const int o = a[q] & 1;
+        odd = odd || o;
+        lo[q] = (a[q] - o) >> 1;
+        hi[q] = (a[q] + o) >> 1;
+    }
+    const int64_t cl = lo[0] + lo[1] * Lc.sy + lo[2] * Lc.sz;
+    const int64_t ch = hi[0] + hi[1] * Lc.sy + hi[2] * Lc.sz;
+#pragma unroll
+    for (int f = 0; f <= D; ++f) {
+        const T* e = ec + (int64_t)f * Lc.N;
+        const T val = odd ? (T)0.5 * (e[cl] + e[ch]) : e[cl];
+        xf[(int64_t)f * Lf.N + v] += val;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// reductions (two-stage, deterministic)
+
+constexpr int RED_BLOCKS = 1024;
+
+template <int B>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < B / 64; ++w) r += sh[w];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sumsq_partial(const T* __restrict__ x, int64_t N,
+                                                       int nf, double* __restrict__ partial) {
+    __shared__ double sh[4];
+    for (int f = 0; f < nf; ++f) {
+        double acc = 0;
+        const T* xf = x + (int64_t)f * N;
+        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
+            const double t = (double)xf[e];
+            acc += t * t;
+        }
+        const double s = block_sum<256>(acc, sh);
+        if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int nblk,
+                                                   int nf, double* __restrict__ out) {
+    __shared__ double sh[4];
+    for (int f = 0; f < nf; ++f) {
+        double acc = 0;
+        for (int e = threadIdx.x; e < nblk; e += 256) acc += partial[(int64_t)f * nblk + e];
+        const double s = block_sum<256>(acc, sh);
+        if (threadIdx.x == 0) out[f] = s;
+    }
+}
+
+// multi-dot: partial[i * gridDim + blk] = sum over block range of V_i w
+__global__ __launch_bounds__(256) void k_multidot_partial(const double* __restrict__ V, int64_t ldv,
+                                                          int k, const double* __restrict__ w,
+                                                          int64_t n, double* __restrict__ partial) {
+    __shared__ double sh[4];
+    for (int i = 0; i < k; ++i) {
+        const double* vi = V + (int64_t)i * ldv;
+        double acc = 0;
+        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+            acc += vi[e] * w[e];
+        const double s = block_sum<256>(acc, sh);
+        if (threadIdx.x == 0) partial[(int64_t)i * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_multiaxpy_t(double* __restrict__ y, const double* __restrict__ X,
+                                                     int64_t ldx, int k, const double* __restrict__ c,
+                                                     double alpha, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double acc = 0;
+    for (int i = 0; i < k; ++i) acc += c[i] * X[(int64_t)i * ldx + e];
+    y[e] += alpha * acc;
+}
+
+__global__ __launch_bounds__(256) void k_scale_t(double* __restrict__ y, double a,
+                                                 const double* __restrict__ x, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) y[e] = a * x[e];
+}
+
+__global__ __launch_bounds__(256) void k_axpby_t(double* __restrict__ y, double a,
+                                                 const double* __restrict__ x, double b, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) y[e] = a * x[e] + b * y[e];
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_convert_t(const Ti* __restrict__ in, To* __restrict__ out,
+                                                   int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) out[e] = (To)in[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_t(const T* __restrict__ x, const int32_t* __restrict__ idx,
+                                                  int64_t m, double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < m) out[e] = (double)x[idx[e]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_t(const double* __restrict__ in,
+                                                   const int32_t* __restrict__ idx, int64_t m,
+                                                   T* __restrict__ x) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < m) x[idx[e]] = (T)in[e];
+}
+
+// y = A x, A dense m x m row major; one wavefront per row.
+__global__ __launch_bounds__(256) void k_dense_matvec_t(const double* __restrict__ A, int64_t m,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ y) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= m) return;
+    const double* a = A + row * m;
+    double acc = 0;
+    for (int64_t c = lane; c < m; c += 64) acc += a[c] * x[c];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (lane == 0) y[row] = acc;
+}
+
+// buoyancy load: b_{d-1}(v) = -rho sum_{T ni v, buoyant} |T| / (d+1)
+template <int D>
+__global__ __launch_bounds__(256) void k_buoyancy_bulk(LevelView L, const uint8_t* __restrict__ flag,
+                                                       double rho, double vol, double* __restrict__ b) {
+    constexpr int NS = KuhnTables<D>::NS;
+    int i, j, k;
+    if (!interior_vertex<D>(L, 0, 1, i, j, k)) return;
+    const int64_t v = i + j * L.sy + k * L.sz;
+    const int ph = L.vphase[v];
+    if (ph == SPECIAL) return;
+    b[(int64_t)(D - 1) * L.N + v] = flag[ph] ? -rho * NS * vol / (D + 1) : 0.0;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_buoyancy_special(LevelView L, const uint8_t* __restrict__ flag,
+                                                          double rho, double vol, double* __restrict__ b) {
+    constexpr int NS = KuhnTables<D>::NS;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= L.spec_off[D + 1]) return;
+    const int64_t v = L.spec[s];
+    int ijk[3];
+    vertex_ijk<D>(L, v, ijk);
+    double acc = 0;
+    for (int sl = 0; sl < NS; ++sl) {
+        const int ph = L.spec_eph[s * NS + sl];
+        if (ph != OUTSIDE && flag[ph]) acc += vol;
+    }
+    b[(int64_t)(D - 1) * L.N + v] = on_boundary<D>(L, ijk) ? 0.0 : -rho * acc / (D + 1);
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+
+static inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t32, size_t bytes32) {
+    hipError_t e;
+    if (dim == 3) {
+        if (bytes64 != sizeof(ElemTables<3, double>) || bytes32 != sizeof(ElemTables<3, float>))
+            return hipErrorInvalidValue;
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_e3d), t64, bytes64);
+        if (e != hipSuccess) return e;
+        return hipMemcpyToSymbol(HIP_SYMBOL(g_e3f), t32, bytes32);
+    }
+    if (bytes64 != sizeof(ElemTables<2, double>) || bytes32 != sizeof(ElemTables<2, float>))
+        return hipErrorInvalidValue;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_e2d), t64, bytes64);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_e2f), t32, bytes32);
+}
+
+template <int D, int F, int BLK, int MODE, typename T>
+static hipError_t apply_t(const LevelView& L, const T* x, const T* b, T* y, hipStream_t s) {
+    const int64_t nb = interior_blocks<D>(L.n, 1);
+    if (nb > 0)
+        hipLaunchKernelGGL((k_apply_bulk<D, F, BLK, MODE, T>), dim3((unsigned)nb), dim3(BX, BY), 0, s,
+                           L, x, b, y);
+    const int64_t ns = L.spec_off[D + 1];
+    if (ns > 0)
+        hipLaunchKernelGGL((k_apply_special<D, F, BLK, MODE, T>), grid1(ns), dim3(256), 0, s, L, x, b, y);
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+static hipError_t apply_d(const LevelView& L, int form, int block, int mode, const T* x, const T* b,
+                          T* y, hipStream_t s) {
+#define ISS_AP(F, BL, MO) \
+    if (form == F && block == BL && mode == MO) return apply_t<D, F, BL, MO, T>(L, x, b, y, s);
+    ISS_AP(0, 0, 0) ISS_AP(0, 0, 1) ISS_AP(0, 1, 0) ISS_AP(0, 1, 1)
+    ISS_AP(1, 0, 0) ISS_AP(1, 0, 1) ISS_AP(1, 1, 0) ISS_AP(1, 1, 1)
+    ISS_AP(2, 0, 0) ISS_AP(2, 0, 1) ISS_AP(2, 1, 0) ISS_AP(2, 1, 1)
+#undef ISS_AP
+    return hipErrorInvalidValue;
+}
+
+hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, const void* x,
+                   const void* b, void* y, hipStream_t s) {
+    if (prec == PREC_F64) {
+        if (L.dim == 3) return apply_d<3, double>(L, form, block, mode, (const double*)x, (const double*)b, (double*)y, s);
+        return apply_d<2, double>(L, form, block, mode, (const double*)x, (const double*)b, (double*)y, s);
+    }
+    if (L.dim == 3) return apply_d<3, float>(L, form, block, mode, (const float*)x, (const float*)b, (float*)y, s);
+    return apply_d<2, float>(L, form, block, mode, (const float*)x, (const float*)b, (float*)y, s);
+}
+
+template <int D, int F, typename T>
+static hipError_t smooth_t(const LevelView& L, double omega, T* x, const T* b, T* delta, hipStream_t s) {
+    const int64_t nbc = interior_blocks<D>(L.n, D + 1);
+    // velocity: forward colours 0..D, then backward colours D..0
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int cc = 0; cc <= D; ++cc) {
+            const int c = pass == 0 ? cc : D - cc;
+            if (nbc > 0) {
+                if (pass == 0)
+                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, false, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, b);
+                else
+                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, true, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, b);
+            }
+            const int64_t ns = L.spec_off[c + 1] - L.spec_off[c];
+            if (ns > 0) {
+                if (pass == 0)
+                    hipLaunchKernelGGL((k_gs_vel_special<D, F, false, T>), grid1(ns), dim3(256), 0, s, L, c, x, b);
+                else
+                    hipLaunchKernelGGL((k_gs_vel_special<D, F, true, T>), grid1(ns), dim3(256), 0, s, L, c, x, b);
+            }
+        }
+    }
+    // pressure: delta = 0, forward colour sweep on C, p += omega delta
+    hipLaunchKernelGGL((k_fill_t<T>), grid1(L.N), dim3(256), 0, s, delta, L.N, (T)0);
+    for (int c = 0; c <= D; ++c) {
+        if (nbc > 0)
+            hipLaunchKernelGGL((k_gs_p_bulk<D, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, b, delta);
+        const int64_t ns = L.spec_off[c + 1] - L.spec_off[c];
+        if (ns > 0)
+            hipLaunchKernelGGL((k_gs_p_special<D, T>), grid1(ns), dim3(256), 0, s, L, c, x, b, delta);
+    }
+    hipLaunchKernelGGL((k_axpy_field<T>), grid1(L.N), dim3(256), 0, s, x + (int64_t)D * L.N, delta,
+                       (T)omega, L.N);
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+static hipError_t smooth_d(const LevelView& L, int form, double omega, T* x, const T* b, T* delta,
+                           hipStream_t s) {
+    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, x, b, delta, s);
+    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, x, b, delta, s);
+    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, x, b, delta, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* x, const void* b,
+                         void* delta, hipStream_t s) {
+    if (prec == PREC_F64) {
+        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)x, (const double*)b, (double*)delta, s);
+        return smooth_d<2, double>(L, form, omega, (double*)x, (const double*)b, (double*)delta, s);
+    }
+    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)x, (const float*)b, (float*)delta, s);
+    return smooth_d<2, float>(L, form, omega, (float*)x, (const float*)b, (float*)delta, s);
+}
+
+hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf, void* rc,
+                      hipStream_t s) {
+    if (prec == PREC_F64) {
+        if (Lf.dim == 3) hipLaunchKernelGGL((k_restrict_t<3, double>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const double*)rf, (double*)rc);
+        else hipLaunchKernelGGL((k_restrict_t<2, double>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const double*)rf, (double*)rc);
+    } else {
+        if (Lf.dim == 3) hipLaunchKernelGGL((k_restrict_t<3, float>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const float*)rf, (float*)rc);
+        else hipLaunchKernelGGL((k_restrict_t<2, float>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const float*)rf, (float*)rc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t k_prolong_add(const LevelView& Lf, const LevelView& Lc, int prec, const void* ec, void* xf,
+                         hipStream_t s) {
+    if (prec == PREC_F64) {
+        if (Lf.dim == 3) hipLaunchKernelGGL((k_prolong_t<3, double>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const double*)ec, (double*)xf);
+        else hipLaunchKernelGGL((k_prolong_t<2, double>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const double*)ec, (double*)xf);
+    } else {
+        if (Lf.dim == 3) hipLaunchKernelGGL((k_prolong_t<3, float>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const float*)ec, (float*)xf);
+        else hipLaunchKernelGGL((k_prolong_t<2, float>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const float*)ec, (float*)xf);
+    }
+    return hipGetLastError();
+}
+
+hipError_t k_fill(int prec, void* x, int64_t n, double value, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (prec == PREC_F64) hipLaunchKernelGGL((k_fill_t<double>), grid1(n), dim3(256), 0, s, (double*)x, n, value);
+    else hipLaunchKernelGGL((k_fill_t<float>), grid1(n), dim3(256), 0, s, (float*)x, n, (float)value);
+    return hipGetLastError();
+}
+
+hipError_t k_convert(int prec_in, const void* in, int prec_out, void* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (prec_in == PREC_F64 && prec_out == PREC_F32)
+        hipLaunchKernelGGL((k_convert_t<double, float>), grid1(n), dim3(256), 0, s, (const double*)in, (float*)out, n);
+    else if (prec_in == PREC_F32 && prec_out == PREC_F64)
+        hipLaunchKernelGGL((k_convert_t<float, double>), grid1(n), dim3(256), 0, s, (const float*)in, (double*)out, n);
+    else if (prec_in == PREC_F64)
+        hipLaunchKernelGGL((k_convert_t<double, double>), grid1(n), dim3(256), 0, s, (const double*)in, (double*)out, n);
+    else
+        hipLaunchKernelGGL((k_convert_t<float, float>), grid1(n), dim3(256), 0, s, (const float*)in, (float*)out, n);
+    return hipGetLastError();
+}
+
+hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* partial, double* out,
+                         hipStream_t s) {
+    const int nblk = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (N + 255) / 256));
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL((k_sumsq_partial<double>), dim3(nblk), dim3(256), 0, s, (const double*)x, N, nf, partial);
+    else
+        hipLaunchKernelGGL((k_sumsq_partial<float>), dim3(nblk), dim3(256), 0, s, (const float*)x, N, nf, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, nf, out);
+    return hipGetLastError();
+}
+
+hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial,
+                      double* out, hipStream_t s) {
+    // partial holds 1024 * 64 doubles: at most 65536 / k blocks
+    const int64_t cap = std::max<int64_t>(1, 65536 / std::max(1, k));
+    const int nblk = (int)std::min<int64_t>(std::min<int64_t>(512, cap), std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(256), 0, s, V, ldv, k, w, n, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, k, out);
+    return hipGetLastError();
+}
+
+hipError_t k_multiaxpy(double* y, const double* X, int64_t ldx, int k, const double* c, double alpha,
+                       int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_multiaxpy_t, grid1(n), dim3(256), 0, s, y, X, ldx, k, c, alpha, n);
+    return hipGetLastError();
+}
+
+hipError_t k_scale(double* y, double a, const double* x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_t, grid1(n), dim3(256), 0, s, y, a, x, n);
+    return hipGetLastError();
+}
+
+hipError_t k_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby_t, grid1(n), dim3(256), 0, s, y, a, x, b, n);
+    return hipGetLastError();
+}
+
+hipError_t k_gather(int prec, const void* x, const int32_t* idx, int64_t m, double* out, hipStream_t s) {
+    if (prec == PREC_F64) hipLaunchKernelGGL((k_gather_t<double>), grid1(m), dim3(256), 0, s, (const double*)x, idx, m, out);
+    else hipLaunchKernelGGL((k_gather_t<float>), grid1(m), dim3(256), 0, s, (const float*)x, idx, m, out);
+    return hipGetLastError();
+}
+
+hipError_t k_scatter(int prec, const double* in, const int32_t* idx, int64_t m, void* x, hipStream_t s) {
+    if (prec == PREC_F64) hipLaunchKernelGGL((k_scatter_t<double>), grid1(m), dim3(256), 0, s, in, idx, m, (double*)x);
+    else hipLaunchKernelGGL((k_scatter_t<float>), grid1(m), dim3(256), 0, s, in, idx, m, (float*)x);
+    return hipGetLastError();
+}
+
+hipError_t k_dense_matvec(const double* A, int64_t m, const double* x, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_matvec_t, grid1(m, 4), dim3(256), 0, s, A, m, x, y);
+    return hipGetLastError();
+}
+
+hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* flag, double rho, double vol, double* b,
+                          hipStream_t s) {
+    const int D = L.dim;
+    const int64_t nb = D == 3 ? interior_blocks<3>(L.n, 1) : interior_blocks<2>(L.n, 1);
+    const int64_t ns = L.spec_off[D + 1];
+    if (D == 3) {
+        if (nb > 0) hipLaunchKernelGGL(k_buoyancy_bulk<3>, dim3((unsigned)nb), dim3(BX, BY), 0, s, L, flag, rho, vol, b);
+        if (ns > 0) hipLaunchKernelGGL(k_buoyancy_special<3>, grid1(ns), dim3(256), 0, s, L, flag, rho, vol, b);
+    } else {
+        if (nb > 0) hipLaunchKernelGGL(k_buoyancy_bulk<2>, dim3((unsigned)nb), dim3(BX, BY), 0, s, L, flag, rho, vol, b);
+        if (ns > 0) hipLaunchKernelGGL(k_buoyancy_special<2>, grid1(ns), dim3(256), 0, s, L, flag, rho, vol, b);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace iss
