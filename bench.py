@@ -1,0 +1,248 @@
+"""Benchmark: seconds to a 1e-8 relative residual and stencil GB/s, decoupled
+(interface) vs strain form, on one MI355X.
+
+Workload (default): sinker_3d -- unit cube as 2 x 2 x 2 macro cubes (48 Kuhn
+tetrahedra) refined 7 times (257^3 vertices, 6.67e7 unknowns u, v, w, p),
+8 seeded spheres (seed 0) with viscosity 1e4 inside and 1 outside, buoyancy
+rho = 1 inside, no-slip walls.  Synthetic, seeded, generated on the device by
+the library (iss_rhs_buoyancy).  One "step" is one complete solve from x = 0
+to ||b - K x|| <= 1e-8 ||b|| with the interface (decoupled + a_tr interface
+rows) form in FP64: FGMRES(150) with one Uzawa V(5,5) cycle per iteration
+(omega 0.6, element-averaged coarse viscosity, strain form on the coarser
+levels as in the paper's coarse-grid swap); the strain form is timed with the
+same solver.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sinker_3d")
+    ap.add_argument("--levels", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--omega", type=float, default=0.6)
+    ap.add_argument("--nu", type=int, default=5, help="pre- and post-smoothing steps")
+    ap.add_argument("--restart", type=int, default=150)
+    ap.add_argument("--maxit", type=int, default=400)
+    ap.add_argument("--outer", default="fgmres")
+    ap.add_argument("--coarse-mu", default="average", choices=["average", "centroid"])
+    ap.add_argument("--forms", default="interface,strain")
+    ap.add_argument("--coarse-form", default="strain", choices=["same", "strain", "interface", "gradient"])
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="no solves: smoothing steps, applies and a plain copy (for profiler runs)")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="solves only, no apply/smoother timing")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def event_time(fn, reps):
+    """Average milliseconds of fn() over reps calls, HIP events on torch's
+    current stream (the stream the library launches on)."""
+    import torch
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def cpu_baseline(w, its_gpu, omega, nu, restart):
+    """The oracle (explicit CSR, same algorithm) on the host: an FGMRES solve
+    of the same workload at a reduced level, timed, scaled to the full
+    lattice by vertex count and to the GPU's iteration count."""
+    code = r"""
+import json, sys, time, numpy as np
+sys.path.insert(0, %r)
+import iss_inputs
+from oracle import multigrid as mg, problem as oprob
+w = iss_inputs.workload(%r, seed=%d, levels=%d)
+H = mg.Hierarchy(w['dim'], w['macro'], w['levels'], w['coarse'], w['inclusions'], w['mu'], 'interface',
+                 omega=%r, nu1=%d, nu2=%d, coarse_mu='average', coarse_form='strain')
+lv = H.levels[w['levels']]
+b = oprob.rhs_buoyancy(w['dim'], w['n'], lv.disc.elems, lv.disc.phase_e, w['buoyant']) * lv.free
+t = time.time()
+x, h = mg.solve_fgmres(H, b, rtol=1e-8, restart=%d, maxit=%d)
+dt = time.time() - t
+print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h[-1])}))
+"""
+    lv_small = min(w["levels"], 4)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, restart, 25)
+    out = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, env=env, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    per_it_vertex = r["seconds"] / max(r["its"], 1) / r["N"]
+    N_full = (w["n"] + 1) ** w["dim"]
+    est = per_it_vertex * N_full * its_gpu
+    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": "oracle FGMRES + Uzawa V-cycle (same settings) on %s refined %d times (%d vertices), %d iterations "
+                      "in %.1f s, scaled by vertex count to %d vertices and to the GPU's %d "
+                      "iterations" % (w["name"], lv_small, r["N"], r["its"], r["seconds"], N_full, its_gpu)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import iss_inputs
+    from paper_1604_07994_amd import Problem
+
+    w = iss_inputs.workload(args.workload, seed=args.seed, levels=args.levels)
+    w["seed"] = args.seed
+    dev = torch.device("cuda:0")
+    forms = args.forms.split(",")
+    t0 = time.time()
+    P = Problem.from_workload(w, outer=args.outer, omega=args.omega, restart=args.restart,
+                              coarse_mu=args.coarse_mu, nu1=args.nu, nu2=args.nu,
+                              coarse_form=None if args.coarse_form == "same" else args.coarse_form)
+    log("setup %.1f s, n = %d" % (time.time() - t0, w["n"]))
+    nvec = P.vector_size()
+    N = P.num_vertices()
+    cls, nif, nbd = P.vertex_class()
+    b = torch.zeros(nvec, dtype=torch.float64, device=dev)
+    P.rhs_buoyancy(b, w["buoyant"] or [1])
+    x = torch.zeros_like(b)
+
+    if args.kernels_only:
+        # fixed, small launch sequence for profiler runs: one smoothing step
+        # per form, the stencil applies, and a plain device copy of known
+        # size (scales the HBM byte counters)
+        xr = torch.rand(nvec, dtype=torch.float64, device=dev)
+        y = torch.empty_like(xr)
+        for _ in range(args.reps):
+            for form in forms:
+                P.smooth(form, x, b, 1)
+            for form in forms:
+                P.apply(form, xr, y, block="velocity")
+                P.apply(form, xr, y, block="full")
+            torch.mul(xr, 1.0, out=y)        # plain read + write of one vector
+        torch.cuda.synchronize()
+        log("kernels-only: %d reps, elementwise copy of %d bytes read + written per rep"
+            % (args.reps, xr.numel() * 8))
+        return
+
+    results = {}
+    for form in forms:
+        for _ in range(args.warmup):
+            x.zero_()
+            info = P.solve(form, x, b, rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+            log("warmup %s: its %d relres %.2e %.3f s" % (form, info["iterations"], info["relres"], info["seconds"]))
+        steps = args.steps if form == forms[0] else max(1, min(args.steps, 2))
+        times = []
+        for _ in range(steps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = P.solve(form, x, b, rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            log("%s: its %d relres %.2e %.3f s" % (form, info["iterations"], info["relres"], times[-1]))
+        results[form] = {"seconds": sorted(times)[len(times) // 2], "all": times,
+                         "iterations": info["iterations"], "relres": info["relres"],
+                         "status": info["status"]}
+    fp32 = None
+    if not args.no_fp32:
+        x.zero_()
+        P.solve(forms[0], x, b, prec="fp32", rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = P.solve(forms[0], x, b, prec="fp32", rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+        torch.cuda.synchronize()
+        fp32 = {"seconds": time.perf_counter() - t, "iterations": info["iterations"],
+                "relres": info["relres"], "status": info["status"]}
+        log("fp32-preconditioned %s: its %d relres %.2e %.3f s" % (forms[0], info["iterations"], info["relres"], fp32["seconds"]))
+
+    apply_gbs = {}
+    smooth_ms = {}
+    if not args.quick:
+        xr = torch.rand(nvec, dtype=torch.float64, device=dev)
+        y = torch.empty_like(xr)
+        for form in ("interface", "strain", "gradient"):
+            for block, bpv in (("velocity", 6 * 8 + 1), ("full", 8 * 8 + 1)):
+                ms = event_time(lambda: P.apply(form, xr, y, block=block), 20)
+                apply_gbs["%s/%s" % (form, block)] = {"ms": ms, "GBs": bpv * N / ms / 1e6,
+                                                       "bytes_per_vertex": bpv}
+        for form in forms:
+            xs = torch.zeros_like(b)
+            smooth_ms[form] = event_time(lambda: P.smooth(form, xs, b, 1), 5)
+        log("apply GB/s: %s" % {k: round(v["GBs"], 1) for k, v in apply_gbs.items()})
+        log("smoothing step ms: %s" % smooth_ms)
+
+    main_form = forms[0]
+    value = results[main_form]["seconds"]
+    # roofline: the velocity Gauss-Seidel colour phase is the kernel with the
+    # most time in a solve; one smoothing step = 2 (d+1) velocity phases +
+    # (d+1) pressure phases.  Algorithmic bytes of a smoothing step per
+    # vertex: symmetric velocity sweep 2 x 81 B + pressure step 49 B.
+    roof = None
+    if smooth_ms:
+        bytes_step = (2 * 81 + 49) * N
+        ach = bytes_step / (smooth_ms[main_form] * 1e-3) / 1e9
+        roof = {"bound": "hbm",
+                "kernel": "one Uzawa smoothing step, finest level, %s form (1 rhs + 8 velocity colour "
+                          "phases + 1 rhs + 4 pressure colour phases + 2 vector kernels)" % main_form,
+                "algorithmic_bytes": bytes_step, "bytes_per_vertex": 2 * 81 + 49,
+                "ms": smooth_ms[main_form],
+                "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                "traffic": None}
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_baseline(w, results[main_form]["iterations"], args.omega, args.nu, args.restart)
+        except Exception as e:   # reported, never silently replaced
+            cpu = {"error": str(e)[-300:]}
+    out = {
+        "metric": "s to 1e-8 rel. residual & stencil GB/s: decoupled vs strain form, 1 MI355X",
+        "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": value * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%s: %d^3 vertices, %d unknowns, %d spheres mu_in %.0e, %d interface "
+                               "vertices" % (w["name"], w["n"] + 1, nvec, len(w["inclusions"]),
+                                             w["mu"][1], nif),
+                   "solver": "%s + Uzawa V(%d,%d), omega %.2f, restart %d, coarse viscosity %s"
+                             % (args.outer, args.nu, args.nu, args.omega, args.restart, args.coarse_mu),
+                   "parallelism": "single GPU"},
+        "forms": results,
+        "strain_over_interface": (results["strain"]["seconds"] / results["interface"]["seconds"])
+        if "strain" in results and "interface" in results else None,
+        "fp32_preconditioner": fp32,
+        "apply": apply_gbs,
+        "smooth_step_ms": smooth_ms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -68,6 +68,7 @@ enum iss_block { ISS_VELOCITY_ONLY = 0, ISS_FULL_STOKES = 1 };
 enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1 };
 enum iss_outer { ISS_OUTER_RICHARDSON = 0, ISS_OUTER_FGMRES = 1 };
 enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1 };
+enum iss_coarse_mu { ISS_COARSE_MU_CENTROID = 0, ISS_COARSE_MU_AVERAGE = 1 };
 
 /* A viscosity inclusion.  Sphere: a = (cx, cy, cz, r), region |x-c| < r
  * (cz ignored in 2D).  Half-space: a = (axis, threshold, -, -), region
@@ -86,6 +87,20 @@ typedef struct {
     double stab_beta;     /* stabilisation constant beta (1/12)             */
     int outer;            /* ISS_OUTER_RICHARDSON or ISS_OUTER_FGMRES       */
     int restart;          /* FGMRES restart length (default 40)             */
+    int coarse_mu;        /* viscosity of coarse-level elements:
+                           * ISS_COARSE_MU_CENTROID: centroid rule on each
+                           *   level (plain rediscretisation);
+                           * ISS_COARSE_MU_AVERAGE (default): volume average
+                           *   of the nested finest-level viscosities (and of
+                           *   1/mu for C) -- for nested P1 spaces the coarse
+                           *   viscous block is then the Galerkin product
+                           *   P^T A P; averages are binned into <= 254
+                           *   phases per level (< 2% relative width).     */
+    int coarse_form;      /* viscous form used on the levels below the
+                           * finest inside V-cycles: -1 (default) = the form
+                           * of the call; ISS_STRAIN follows the paper's swap
+                           * to the strain form on coarse grids (Sec. 5),
+                           * applied to every coarser level.              */
 } iss_options;
 
 typedef struct {
@@ -124,7 +139,8 @@ int iss_vertex_class(const iss_problem* p, int level, uint8_t* cls,
 
 /* Buoyancy load b = (0, .., 0, -rho sum_{T in buoyant phases} |T|/(d+1), 0)
  * (body force (0,..,0,-rho) on elements of the listed phases) at `level`
- * into device FP64 vector b (overwritten). */
+ * into device FP64 vector b (overwritten).  With ISS_COARSE_MU_AVERAGE only
+ * the finest level carries the problem's phases (ISS_E_INVAL otherwise). */
 int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
                      double rho, double* b, iss_stream_t stream);
 

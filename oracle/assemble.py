@@ -26,7 +26,7 @@ class Discretisation:
     only rows of vertices whose incident elements are all present are
     meaningful."""
 
-    def __init__(self, dim, n, inclusions, mu_table, elems=None):
+    def __init__(self, dim, n, inclusions, mu_table, elems=None, mu_e=None, imu_e=None):
         self.dim, self.n = dim, n
         self.N = mesh.num_vertices(dim, n)
         self.h = 1.0 / n
@@ -34,7 +34,10 @@ class Discretisation:
         self.inclusions = inclusions
         self.mu_table = np.asarray(mu_table, dtype=np.float64)
         self.phase_e = problem.element_phase(dim, n, self.elems, inclusions)
-        self.mu_e = self.mu_table[self.phase_e]
+        # per-element viscosity (viscous blocks) and inverse viscosity
+        # (stabilisation, pressure weights); by default from the phases
+        self.mu_e = self.mu_table[self.phase_e] if mu_e is None else np.asarray(mu_e, np.float64)
+        self.imu_e = 1.0 / self.mu_e if imu_e is None else np.asarray(imu_e, np.float64)
         X = mesh.vertex_coords(dim, n)[self.elems]
         self.G, self.vol = fem.simplex_geometry(X)
         self.interface = problem.interface_vertices(dim, n, self.elems, self.mu_e)
@@ -102,7 +105,7 @@ class Discretisation:
 
     def stabilisation(self):
         """C (N x N): c(p, q) = sum_T beta h^2/mu_T (grad p, grad q)_T."""
-        Ce = fem.stabilisation_element_matrices(self.G, self.vol, self.mu_e, self.h)
+        Ce = fem.stabilisation_element_matrices(self.G, self.vol, 1.0 / self.imu_e, self.h)
         return self._coo(Ce, self.elems, self.elems, (self.N, self.N))
 
     def mass(self):
@@ -140,3 +143,55 @@ def sampled_rows(dim, n, inclusions, mu_table, verts):
     """
     elems = mesh.incident_elements(dim, n, verts)
     return Discretisation(dim, n, inclusions, mu_table, elems=elems)
+
+
+def sampled_stokes_rows(dim, n, inclusions, mu_table, verts, form, x):
+    """Rows of y = K x at the vertices ``verts`` (all d+1 fields) without
+    assembling K globally: the element matrices of the elements incident to
+    the sample are scattered only into sample rows.  Dirichlet masking as in
+    Discretisation.stokes.  Returns Y with Y[f, i] = y[f * N + verts[i]]."""
+    verts = np.unique(np.asarray(verts, dtype=np.int64))
+    D = sampled_rows(dim, n, inclusions, mu_table, verts)
+    N = D.N
+    d = dim
+    lookup = {int(v): i for i, v in enumerate(verts)}
+    key = {'gradient': 'lap', 'strain': 'sym', 'interface': 'tr', 'tr': 'tr'}[form]
+    Ke = fem.viscous_element_matrices(D.G, D.vol, D.mu_e, key)
+    if form == 'interface':
+        # rows of non-interface vertices come from the Laplacian form
+        Kl = fem.viscous_element_matrices(D.G, D.vol, D.mu_e, 'lap')
+    Be = fem.divergence_element_matrices(D.G, D.vol)
+    Ce = fem.stabilisation_element_matrices(D.G, D.vol, D.mu_e, D.h)
+    bnd = D.boundary
+    free_u = lambda v: ~bnd[v]
+    Y = np.zeros((d + 1, len(verts)))
+    E = D.elems
+    for e in range(len(E)):
+        ev = E[e]
+        for a in range(d + 1):
+            va = int(ev[a])
+            if va not in lookup:
+                continue
+            i = lookup[va]
+            # velocity rows (zero on Dirichlet vertices)
+            if not bnd[va]:
+                src = Ke if (form != 'interface' or D.interface[va]) else Kl
+                for l in range(d):
+                    acc = 0.0
+                    for b in range(d + 1):
+                        vb = int(ev[b])
+                        if free_u(vb):
+                            for k in range(d):
+                                acc += src[e, a * d + l, b * d + k] * x[k * N + vb]
+                        acc += Be[e, b, a * d + l] * x[d * N + vb]
+                    Y[l, i] += acc
+            # pressure row
+            acc = 0.0
+            for b in range(d + 1):
+                vb = int(ev[b])
+                if free_u(vb):
+                    for k in range(d):
+                        acc += Be[e, a, b * d + k] * x[k * N + vb]
+                acc -= Ce[e, a, b] * x[d * N + vb]
+            Y[d, i] += acc
+    return verts, Y

@@ -73,9 +73,67 @@ def prolongation(dim, n_coarse):
                          shape=(Nf, Nc))
 
 
+def parent_elements(dim, n_coarse):
+    """Index of the coarse Kuhn element (n_coarse cells per axis) that
+    contains each element of the once-refined lattice.  The meshes are
+    nested, so a fine centroid lies strictly inside its parent; the parent
+    is found by barycentric coordinates in the simplices of its cell."""
+    nf = 2 * n_coarse
+    Ef = mesh.kuhn_elements(dim, nf)
+    cen = mesh.vertex_coords(dim, nf)[Ef].mean(axis=1)
+    cell = np.minimum(np.floor(cen * n_coarse).astype(np.int64), n_coarse - 1)
+    off = mesh.kuhn_offsets(dim)
+    parent = -np.ones(len(Ef), dtype=np.int64)
+    cell_id = mesh.vertex_index(dim, n_coarse - 1, cell)
+    for s in range(off.shape[0]):
+        X = (cell[:, None, :] + off[s][None]) / n_coarse
+        M = np.concatenate([np.ones(X.shape[:2] + (1,)), X], axis=2)
+        rhs = np.concatenate([np.ones((len(cen), 1)), cen], axis=1)[:, :, None]
+        lam = np.linalg.solve(np.transpose(M, (0, 2, 1)), rhs)[:, :, 0]
+        ok = np.all(lam > 1e-12, axis=1) & (parent < 0)
+        parent[ok] = cell_id[ok] * off.shape[0] + s
+    assert (parent >= 0).all()
+    return parent
+
+
+def averaged_coarse_viscosity(dim, n_coarse, mu_f, imu_f, pure_values, nbins=250):
+    """Coarse-element viscosity as the volume average over the nested fine
+    elements (equal volumes under uniform refinement), and the same for
+    1/mu.  For nested P1 spaces the viscous block assembled with these
+    averages equals the Galerkin product P^T A P.
+
+    Reading taken for the per-level representation: averages equal to a
+    viscosity of the problem (pure elements) are kept exactly; the other
+    averages are grouped into ``nbins`` logarithmically spaced bins between
+    the smallest and largest mixed average of the level, and every member
+    of a bin takes the bin's mean of mu and of 1/mu.
+    Returns the unbinned averages (mu, 1/mu) and the binned ones."""
+    parent = parent_elements(dim, n_coarse)
+    nce = n_coarse ** dim * (6 if dim == 3 else 2)
+    kids = np.bincount(parent, minlength=nce)
+    mu_avg = np.bincount(parent, mu_f, minlength=nce) / kids
+    imu_avg = np.bincount(parent, imu_f, minlength=nce) / kids
+    pure = np.zeros(nce, dtype=bool)
+    mu_q, imu_q = mu_avg.copy(), imu_avg.copy()
+    for v in pure_values:
+        hit = (np.abs(mu_avg - v) <= 1e-14 * v) & (np.abs(imu_avg * v - 1.0) < 1e-12)
+        pure |= hit
+        mu_q[hit], imu_q[hit] = v, 1.0 / v
+    if (~pure).any():
+        lm = np.log(mu_avg[~pure])
+        lo, hi = lm.min(), lm.max()
+        t = (lm - lo) / (hi - lo) if hi > lo else np.zeros_like(lm)
+        b = np.minimum(nbins - 1, (t * nbins).astype(np.int64))
+        cnt = np.bincount(b, minlength=nbins)
+        bm = np.bincount(b, mu_avg[~pure], minlength=nbins) / np.maximum(cnt, 1)
+        bi = np.bincount(b, imu_avg[~pure], minlength=nbins) / np.maximum(cnt, 1)
+        mu_q[~pure], imu_q[~pure] = bm[b], bi[b]
+    return mu_avg, imu_avg, mu_q, imu_q
+
+
 class Level:
-    def __init__(self, dim, n, inclusions, mu_table, form):
-        self.disc = assemble.Discretisation(dim, n, inclusions, mu_table)
+    def __init__(self, dim, n, inclusions, mu_table, form, mu_e=None, imu_e=None):
+        self.disc = assemble.Discretisation(dim, n, inclusions, mu_table, mu_e=mu_e, imu_e=imu_e)
         d = self.disc
         self.dim, self.n, self.N = dim, n, d.N
         self.form = form
@@ -89,7 +147,7 @@ class Level:
         self.Cdiag = self.C.diagonal()
         self.colour = colours(dim, n)
         self.free = d.free_mask()
-        self.weights = problem.pressure_weights(dim, n, d.elems, d.mu_e)
+        self.weights = problem.pressure_weights(dim, n, d.elems, 1.0 / d.imu_e)
 
 
 def split(x, dim, N):
@@ -154,12 +212,26 @@ class Hierarchy:
     """Levels n_l = m 2^l for l = coarse..fine (m macro cubes per axis)."""
 
     def __init__(self, dim, m, fine_level, coarse_level, inclusions, mu_table, form,
-                 nu1=3, nu2=3, omega=OMEGA):
+                 nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None):
+        """coarse_mu: 'centroid' rediscretises every level with the centroid
+        rule; 'average' uses averaged_coarse_viscosity below the finest
+        level.  coarse_form: viscous form of the levels below the finest
+        (Sec. 5 swaps to the strain form on the coarse grid); default: the
+        same form on every level."""
         self.dim = dim
         self.levels = {}
         self.P = {}
-        for l in range(coarse_level, fine_level + 1):
-            self.levels[l] = Level(dim, m * 2 ** l, inclusions, mu_table, form)
+        cform = form if coarse_form is None else coarse_form
+        mu_f = imu_f = None
+        for l in range(fine_level, coarse_level - 1, -1):
+            n = m * 2 ** l
+            f = form if l == fine_level else cform
+            if l == fine_level or coarse_mu == 'centroid':
+                self.levels[l] = Level(dim, n, inclusions, mu_table, f)
+                mu_f, imu_f = self.levels[l].disc.mu_e, self.levels[l].disc.imu_e
+            else:
+                mu_f, imu_f, mq, iq = averaged_coarse_viscosity(dim, n, mu_f, imu_f, list(mu_table))
+                self.levels[l] = Level(dim, n, inclusions, mu_table, f, mu_e=mq, imu_e=iq)
             if l > coarse_level:
                 self.P[l] = prolongation(dim, m * 2 ** (l - 1))
         self.fine, self.coarse = fine_level, coarse_level

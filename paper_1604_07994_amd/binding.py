@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libiss.so")
 FORMS = {"gradient": 0, "strain": 1, "interface": 2}
 BLOCKS = {"velocity": 0, "full": 1}
 OUTER = {"richardson": 0, "fgmres": 1}
+COARSE_MU = {"centroid": 0, "average": 1}
 PREC_F64, PREC_F32 = 0, 1
 
 _lib = None
@@ -30,7 +31,8 @@ class Inclusion(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
-                ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int),
+                ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -119,10 +121,12 @@ class Problem:
     """A refined Kuhn-lattice Stokes problem owned by libiss."""
 
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
-                 stab_beta=1.0 / 12.0, outer="richardson", restart=40):
+                 stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
+                 coarse_form=None):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
-        opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart)
+        opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
+                      -1 if coarse_form is None else FORMS[coarse_form])
         incs = inclusions_to_c(inclusions)
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()

@@ -156,6 +156,12 @@ struct Level {
     uint8_t* d_spec_eph = nullptr;
     std::vector<uint8_t> cls;       // per vertex: bit0 interface, bit1 boundary
     std::vector<uint8_t> elem_phase;// per element (cell * NT + type)
+    std::vector<double> mu_tab, imu_tab;     // viscosity and 1/viscosity per phase
+    std::vector<double> emu, eimu;  // per element averages (setup only)
+    double* d_mu64 = nullptr;
+    double* d_imu64 = nullptr;
+    float* d_mu32 = nullptr;
+    float* d_imu32 = nullptr;
     int64_t ninterface = 0, nboundary = 0;
     void* w_x[2] = {nullptr, nullptr};
     void* w_b[2] = {nullptr, nullptr};
@@ -198,6 +204,7 @@ struct iss_problem {
     double* d_h = nullptr;          // m + 2 entries
     uint8_t* d_flag = nullptr;      // 256 buoyancy flags
     double* h_pinned = nullptr;     // 8192 doubles of pinned host memory
+    int64_t reorth_count = 0;       // second Gram-Schmidt passes (diagnostics)
     std::vector<void*> allocs;
 };
 
@@ -236,16 +243,14 @@ int element_phase(const iss_problem* p, const double (&c)[3]) {
     return 0;
 }
 
+// Element phases of level l by the centroid rule with the problem's table.
 template <int D>
-int setup_level(iss_problem* p, int l) {
+void centroid_phases(iss_problem* p, int l) {
     constexpr auto& K = Kuhn<D>::T;
-    constexpr int NT = KuhnTables<D>::NT, NS = KuhnTables<D>::NS;
+    constexpr int NT = KuhnTables<D>::NT;
     Level& L = p->lv[l];
     const int n = p->macro << l;
-    const int64_t n1 = n + 1;
-    const int64_t N = (D == 3) ? n1 * n1 * n1 : n1 * n1;
     const int64_t ncell = (D == 3) ? (int64_t)n * n * n : (int64_t)n * n;
-    // element phases
     L.elem_phase.assign(ncell * NT, 0);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < ncell; ++c) {
@@ -261,6 +266,145 @@ int setup_level(iss_problem* p, int l) {
             L.elem_phase[c * NT + ty] = (uint8_t)element_phase(p, cen);
         }
     }
+    L.mu_tab.assign(p->mu.begin(), p->mu.end());
+    L.imu_tab.resize(256);
+    for (int i = 0; i < 256; ++i) L.imu_tab[i] = 1.0 / L.mu_tab[i];
+}
+
+// Kuhn type of the simplex of a unit cell that contains a point with
+// fractional coordinates f (strictly inside): the axis order of decreasing
+// f is the permutation of the type.
+template <int D>
+int kuhn_type_of(const double (&f)[3]) {
+    constexpr auto& K = Kuhn<D>::T;
+    for (int ty = 0; ty < KuhnTables<D>::NT; ++ty) {
+        bool ok = true;
+        for (int s = 0; s + 1 < D; ++s) {
+            int a0 = -1, a1 = -1;
+            for (int a = 0; a < D; ++a) {
+                if (K.type_vert[ty][s + 1][a] != K.type_vert[ty][s][a]) a0 = a;
+                if (K.type_vert[ty][s + 2][a] != K.type_vert[ty][s + 1][a]) a1 = a;
+            }
+            ok = ok && f[a0] >= f[a1];
+        }
+        if (ok) return ty;
+    }
+    return 0;
+}
+
+// Element viscosity of level l as the volume average over the nested
+// elements of level l+1 (each coarse simplex is the union of its 8 (4 in
+// 2D) equal-volume children).  For nested P1 spaces this makes the coarse
+// viscous block the Galerkin product P^T A P; 1/viscosity is averaged the
+// same way for the stabilisation block.
+template <int D>
+void averaged_viscosity(iss_problem* p, int l) {
+    constexpr auto& K = Kuhn<D>::T;
+    constexpr int NT = KuhnTables<D>::NT;
+    Level& F = p->lv[l + 1];
+    Level& L = p->lv[l];
+    const int nf = p->macro << (l + 1), nc = p->macro << l;
+    const int64_t ncf = (D == 3) ? (int64_t)nf * nf * nf : (int64_t)nf * nf;
+    const int64_t ncc = (D == 3) ? (int64_t)nc * nc * nc : (int64_t)nc * nc;
+    if (F.emu.empty()) {       // finest level: from the phases
+        F.emu.resize(ncf * NT);
+        F.eimu.resize(ncf * NT);
+        for (int64_t e = 0; e < ncf * NT; ++e) {
+            F.emu[e] = F.mu_tab[F.elem_phase[e]];
+            F.eimu[e] = F.imu_tab[F.elem_phase[e]];
+        }
+    }
+    L.emu.assign(ncc * NT, 0.0);
+    L.eimu.assign(ncc * NT, 0.0);
+    const double w = 1.0 / (D == 3 ? 8.0 : 4.0);
+    for (int64_t c = 0; c < ncf; ++c) {
+        const int ci = (int)(c % nf), cj = (int)((c / nf) % nf), ck = (D == 3) ? (int)(c / ((int64_t)nf * nf)) : 0;
+        const int cf[3] = {ci, cj, ck};
+        for (int ty = 0; ty < NT; ++ty) {
+            double cen[3] = {0, 0, 0};
+            for (int b = 0; b <= D; ++b)
+                for (int a = 0; a < D; ++a) cen[a] += cf[a] + K.type_vert[ty][b][a];
+            int cc[3] = {0, 0, 0};
+            double fr[3] = {0, 0, 0};
+            for (int a = 0; a < D; ++a) {
+                const double x = cen[a] / (D + 1) / 2.0;      // coarse lattice units
+                cc[a] = std::min((int)std::floor(x), nc - 1);
+                fr[a] = x - cc[a];
+            }
+            const int tyc = kuhn_type_of<D>(fr);
+            const int64_t ce = (D == 3) ? cc[0] + (int64_t)nc * (cc[1] + (int64_t)nc * cc[2]) : cc[0] + (int64_t)nc * cc[1];
+            L.emu[ce * NT + tyc] += w * F.emu[c * NT + ty];
+            L.eimu[ce * NT + tyc] += w * F.eimu[c * NT + ty];
+        }
+    }
+    std::vector<double>().swap(F.emu);
+    std::vector<double>().swap(F.eimu);
+    // phases: one per distinct pure viscosity of the problem, then at most
+    // 250 logarithmic bins of the mixed averages (relative width < 2% for
+    // contrasts up to 1e4; each bin stores the mean of its members)
+    std::vector<double> tab_mu, tab_imu;
+    std::vector<double> sum_mu(256, 0.0), sum_imu(256, 0.0), cnt(256, 0.0);
+    double lo = 1e300, hi = -1e300;
+    const int64_t ne = ncc * NT;
+    L.elem_phase.assign(ne, 0);
+    std::vector<int> pure_of(p->mu.size(), -1);
+    std::vector<double> pure_vals;
+    auto pure_index = [&](double m, double im) -> int {
+        for (size_t k = 0; k < pure_vals.size(); ++k)
+            if (pure_vals[k] == m && std::fabs(im * m - 1.0) < 1e-12) return (int)k;
+        return -1;
+    };
+    for (int64_t e = 0; e < ne; ++e) {
+        const double m = L.emu[e], im = L.eimu[e];
+        bool pure = false;
+        for (size_t k = 0; k < p->mu.size() && k < 254; ++k)
+            if (std::fabs(m - p->mu[k]) <= 1e-14 * p->mu[k] && std::fabs(im * p->mu[k] - 1.0) < 1e-12) {
+                if (pure_index(p->mu[k], 1.0 / p->mu[k]) < 0) pure_vals.push_back(p->mu[k]);
+                pure = true;
+                break;
+            }
+        if (!pure) { lo = std::min(lo, std::log(m)); hi = std::max(hi, std::log(m)); }
+    }
+    const int npure = (int)pure_vals.size();
+    const int nbins = std::max(1, std::min(250, 254 - npure));
+    std::vector<int> bin_of_elem(ne, -1);
+    for (int64_t e = 0; e < ne; ++e) {
+        const double m = L.emu[e], im = L.eimu[e];
+        int k = -1;
+        for (int q = 0; q < npure; ++q)
+            if (std::fabs(m - pure_vals[q]) <= 1e-14 * pure_vals[q] && std::fabs(im * pure_vals[q] - 1.0) < 1e-12) k = q;
+        if (k < 0) {
+            const double t = (hi > lo) ? (std::log(m) - lo) / (hi - lo) : 0.0;
+            k = npure + std::min(nbins - 1, (int)(t * nbins));
+        }
+        bin_of_elem[e] = k;
+        sum_mu[k] += m;
+        sum_imu[k] += im;
+        cnt[k] += 1;
+    }
+    std::vector<int> remap(256, -1);
+    L.mu_tab.assign(256, 1.0);
+    L.imu_tab.assign(256, 1.0);
+    int nph = 0;
+    for (int k = 0; k < npure + nbins; ++k) {
+        if (cnt[k] == 0) continue;
+        remap[k] = nph;
+        L.mu_tab[nph] = (k < npure) ? pure_vals[k] : sum_mu[k] / cnt[k];
+        L.imu_tab[nph] = (k < npure) ? 1.0 / pure_vals[k] : sum_imu[k] / cnt[k];
+        ++nph;
+    }
+    for (int64_t e = 0; e < ne; ++e) L.elem_phase[e] = (uint8_t)remap[bin_of_elem[e]];
+    if (l == p->coarse) { std::vector<double>().swap(L.emu); std::vector<double>().swap(L.eimu); }
+}
+
+template <int D>
+int setup_level(iss_problem* p, int l) {
+    constexpr auto& K = Kuhn<D>::T;
+    constexpr int NT = KuhnTables<D>::NT, NS = KuhnTables<D>::NS;
+    Level& L = p->lv[l];
+    const int n = p->macro << l;
+    const int64_t n1 = n + 1;
+    const int64_t N = (D == 3) ? n1 * n1 * n1 : n1 * n1;
     // vertex classes
     std::vector<uint8_t> vphase(N);
     L.cls.assign(N, 0);
@@ -291,7 +435,7 @@ int setup_level(iss_problem* p, int l) {
             if (first < 0) first = ph[s];
             else {
                 if (ph[s] != first) mixed_phase = true;
-                if (p->mu[ph[s]] != p->mu[first]) mixed_mu = true;
+                if (L.mu_tab[ph[s]] != L.mu_tab[first]) mixed_mu = true;
             }
         }
         if (mixed_mu) { L.cls[v] |= 1; ++nif; }
@@ -317,6 +461,14 @@ int setup_level(iss_problem* p, int l) {
     }
     for (int c = D + 1; c < 5; ++c) off[c] = (int64_t)spec.size();
     int rc;
+    {
+        std::vector<float> m32(256), im32(256);
+        for (int i = 0; i < 256; ++i) { m32[i] = (float)L.mu_tab[i]; im32[i] = (float)L.imu_tab[i]; }
+        if ((rc = dev_upload(p, &L.d_mu64, L.mu_tab.data(), 256))) return rc;
+        if ((rc = dev_upload(p, &L.d_imu64, L.imu_tab.data(), 256))) return rc;
+        if ((rc = dev_upload(p, &L.d_mu32, m32.data(), 256))) return rc;
+        if ((rc = dev_upload(p, &L.d_imu32, im32.data(), 256))) return rc;
+    }
     if ((rc = dev_upload(p, &L.d_vphase, vphase.data(), vphase.size()))) return rc;
     if ((rc = dev_upload(p, &L.d_spec, spec.data(), spec.size()))) return rc;
     if ((rc = dev_upload(p, &L.d_spec_eph, eph.data(), eph.size()))) return rc;
@@ -330,10 +482,10 @@ int setup_level(iss_problem* p, int l) {
     V.spec = L.d_spec;
     V.spec_eph = L.d_spec_eph;
     for (int c = 0; c < 5; ++c) V.spec_off[c] = off[c];
-    V.mu64 = p->d_mu64;
-    V.imu64 = p->d_imu64;
-    V.mu32 = p->d_mu32;
-    V.imu32 = p->d_imu32;
+    V.mu64 = L.d_mu64;
+    V.imu64 = L.d_imu64;
+    V.mu32 = L.d_mu32;
+    V.imu32 = L.d_imu32;
     const double h = 1.0 / n;
     V.sA = std::pow(h, D - 2);
     V.sB = std::pow(h, D - 1);
@@ -384,7 +536,7 @@ void coarse_matrix(const iss_problem* p, int form, std::vector<double>& Kd, int6
         const int ci = (int)(c % n), cj = (int)((c / n) % n), ck = (D == 3) ? (int)(c / ((int64_t)n * n)) : 0;
         for (int ty = 0; ty < NT; ++ty) {
             const int ph = L.elem_phase[c * NT + ty];
-            const double mu = p->mu[ph];
+            const double mu = L.mu_tab[ph], imu = L.imu_tab[ph];
             int64_t vid[D + 1];
             for (int b = 0; b <= D; ++b)
                 vid[b] = (ci + K.type_vert[ty][b][0]) + n1 * (cj + K.type_vert[ty][b][1]) +
@@ -393,7 +545,7 @@ void coarse_matrix(const iss_problem* p, int form, std::vector<double>& Kd, int6
             for (int a = 0; a < D; ++a) vol /= n;
             vol /= (D == 3 ? 6.0 : 2.0);
             for (int a = 0; a <= D; ++a) {
-                w[vid[a]] += vol / ((D + 1) * mu);
+                w[vid[a]] += vol * imu / (D + 1);
                 for (int b = 0; b <= D; ++b) {
                     // velocity-velocity and B^T / B couplings
                     for (int l = 0; l < D; ++l) {
@@ -411,7 +563,7 @@ void coarse_matrix(const iss_problem* p, int form, std::vector<double>& Kd, int6
                         const int64_t cc = cmap[(size_t)k * N + vid[b]];
                         if (cc >= 0) Kd[(size_t)rp * M + cc] += sB * E.Bel[ty][a][b * D + k];
                     }
-                    Kd[(size_t)rp * M + cmap[(size_t)D * N + vid[b]]] -= sC / mu * E.Cel[ty][a][b];
+                    Kd[(size_t)rp * M + cmap[(size_t)D * N + vid[b]]] -= sC * imu * E.Cel[ty][a][b];
                 }
             }
         }
@@ -529,16 +681,18 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, hi
     Level& L = p->lv[l];
     Level& Lc = p->lv[l - 1];
     const size_t es = prec == PREC_F64 ? 8 : 4;
-    void* delta = (char*)L.w_r[prec] + (size_t)p->dim * L.v.N * es;
+    void* work = L.w_r[prec];
+    (void)es;
     for (int i = 0; i < p->opt.nu1; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, delta, s));
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, work, s));
     ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
     ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
     ISS_HIP(k_fill(prec, Lc.w_x[prec], (int64_t)(p->dim + 1) * Lc.v.N, 0.0, s));
-    if ((rc = vcycle(p, l - 1, form, prec, Lc.w_x[prec], Lc.w_b[prec], s))) return rc;
+    const int cform = (p->opt.coarse_form >= 0) ? p->opt.coarse_form : form;
+    if ((rc = vcycle(p, l - 1, cform, prec, Lc.w_x[prec], Lc.w_b[prec], s))) return rc;
     ISS_HIP(k_prolong_add(L.v, Lc.v, prec, Lc.w_x[prec], x, s));
     for (int i = 0; i < p->opt.nu2; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, delta, s));
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, work, s));
     return ISS_OK;
 }
 
@@ -603,7 +757,7 @@ int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
     const int m = std::max(1, p->opt.restart);
     int rc;
     if ((rc = ensure_krylov(p, m))) return rc;
-    if ((rc = ensure_coarse(p, form))) return rc;
+    if ((rc = ensure_coarse(p, (p->levels > p->coarse && p->opt.coarse_form >= 0) ? p->opt.coarse_form : form))) return rc;
     double sq[4];
     if ((rc = field_norms(p, PREC_F64, b, N, D + 1, sq, s))) return rc;
     const double nb = total_norm(sq, D + 1);
@@ -650,18 +804,29 @@ int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
                 for (; j < m && its < maxit; ++j) {
                     if ((rc = precondition(p, form, prec, V + (size_t)j * n, Z + (size_t)j * n, s))) return rc;
                     ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_APPLY, PREC_F64, Z + (size_t)j * n, nullptr, w, s));
-                    // h = V^T w ; w -= V h ; twice
-                    for (int pass = 0; pass < 2; ++pass) {
-                        double* hp = dh + (pass == 0 ? 0 : (m + 2));
-                        ISS_HIP(k_multidot(V, n, j + 1, w, n, p->d_partial, hp, s));
-                        ISS_HIP(k_multiaxpy(w, V, n, j + 1, hp, -1.0, n, s));
-                    }
-                    ISS_HIP(k_field_sumsq(PREC_F64, w, n, 1, p->d_partial, dh + (2 * m + 3), s));
+                    // classical Gram-Schmidt h = V^T w, w -= V h; a second pass
+                    // only when the norm drops below 1/sqrt(2) of its value
+                    // before projection (Daniel-Gragg-Kaufman-Stewart test)
                     double* hh = p->h_pinned;
+                    ISS_HIP(k_multidot(V, n, j + 1, w, n, p->d_partial, dh, s, 1));
+                    ISS_HIP(k_multiaxpy(w, V, n, j + 1, dh, -1.0, n, s));
+                    ISS_HIP(k_field_sumsq(PREC_F64, w, n, 1, p->d_partial, dh + (2 * m + 3), s));
                     ISS_HIP(hipMemcpyAsync(hh, dh, (2 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, s));
                     ISS_HIP(hipStreamSynchronize(s));
-                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[m + 2 + i];
-                    const double hn = std::sqrt(hh[2 * m + 3]);
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
+                    const double before = std::sqrt(std::max(hh[j + 1], 0.0));
+                    double hn = std::sqrt(std::max(hh[2 * m + 3], 0.0));
+                    if (hn < 0.7071067811865476 * before) {
+                        double* hp = dh + (m + 2);
+                        ISS_HIP(k_multidot(V, n, j + 1, w, n, p->d_partial, hp, s, 0));
+                        ISS_HIP(k_multiaxpy(w, V, n, j + 1, hp, -1.0, n, s));
+                        ISS_HIP(k_field_sumsq(PREC_F64, w, n, 1, p->d_partial, dh + (2 * m + 3), s));
+                        ISS_HIP(hipMemcpyAsync(hh, dh, (2 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+                        ISS_HIP(hipStreamSynchronize(s));
+                        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hh[m + 2 + i];
+                        hn = std::sqrt(std::max(hh[2 * m + 3], 0.0));
+                        ++p->reorth_count;
+                    }
                     H[(size_t)(j + 1) * m + j] = hn;
                     if (hn > 0) ISS_HIP(k_scale(V + (size_t)(j + 1) * n, 1.0 / hn, w, n, s));
                     for (int i = 0; i < j; ++i) {
@@ -738,6 +903,8 @@ int iss_default_options(iss_options* o) {
     o->stab_beta = 1.0 / 12.0;
     o->outer = ISS_OUTER_RICHARDSON;
     o->restart = 40;
+    o->coarse_mu = ISS_COARSE_MU_AVERAGE;
+    o->coarse_form = -1;
     return ISS_OK;
 }
 
@@ -782,7 +949,9 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     if (opt) p->opt = *opt;
     else iss_default_options(&p->opt);
     if (p->opt.nu1 < 0 || p->opt.nu2 < 0 || !(p->opt.stab_beta > 0) || p->opt.restart < 1 ||
-        (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES)) {
+        (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES) ||
+        (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
+        p->opt.coarse_form < -1 || p->opt.coarse_form > 2) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }
@@ -820,8 +989,14 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
             if (e != hipSuccess) { rc = fail(ISS_E_HIP, std::string("upload tables: ") + hipGetErrorString(e)); break; }
         }
         p->lv.resize(levels + 1);
-        for (int l = coarse_level; l <= levels && rc == ISS_OK; ++l)
+        for (int l = levels; l >= coarse_level && rc == ISS_OK; --l) {
+            if (l == levels || p->opt.coarse_mu == ISS_COARSE_MU_CENTROID) {
+                if (dim == 3) centroid_phases<3>(p, l); else centroid_phases<2>(p, l);
+            } else {
+                if (dim == 3) averaged_viscosity<3>(p, l); else averaged_viscosity<2>(p, l);
+            }
             rc = (dim == 3) ? setup_level<3>(p, l) : setup_level<2>(p, l);
+        }
         if (rc) break;
         // keep element phases only where the coarse matrix needs them
         for (int l = coarse_level + 1; l <= levels; ++l) std::vector<uint8_t>().swap(p->lv[l].elem_phase);
@@ -859,6 +1034,8 @@ int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
     if (!p || !b || (nbuoyant > 0 && !phases)) return fail(ISS_E_INVAL, "null argument");
     int rc;
     if ((rc = check_level(p, level))) return rc;
+    if (level != p->levels && p->opt.coarse_mu != ISS_COARSE_MU_CENTROID)
+        return fail(ISS_E_INVAL, "buoyancy load needs the finest level (coarse phases are viscosity bins)");
     hipStream_t s = (hipStream_t)stream;
     uint8_t flag[256] = {0};
     for (int i = 0; i < nbuoyant; ++i) {
@@ -912,9 +1089,10 @@ int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps, void* 
     if ((rc = ensure_work(p, level, prec))) return rc;
     Level& L = p->lv[level];
     const size_t es = prec == PREC_F64 ? 8 : 4;
-    void* delta = (char*)L.w_r[prec] + (size_t)p->dim * L.v.N * es;
+    void* work = L.w_r[prec];
+    (void)es;
     for (int i = 0; i < nsteps; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, delta, (hipStream_t)stream));
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, work, (hipStream_t)stream));
     return ISS_OK;
 }
 

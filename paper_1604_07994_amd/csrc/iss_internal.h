@@ -40,8 +40,9 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
                          size_t bytes32);
 hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec,
                    const void* x, const void* b, void* y, hipStream_t s);
+// one Uzawa step; work holds d+1 fields of scratch (the level's r vector)
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* x,
-                         const void* b, void* delta, hipStream_t s);
+                         const void* b, void* work, hipStream_t s);
 hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf,
                       void* rc, hipStream_t s);
 hipError_t k_prolong_add(const LevelView& Lf, const LevelView& Lc, int prec, const void* ec,
@@ -53,9 +54,10 @@ hipError_t k_convert(int prec_in, const void* in, int prec_out, void* out, int64
 // FP64), using `partial` (device, >= 1024 * nf doubles) as scratch.
 hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* partial,
                          double* out, hipStream_t s);
-// out[i] = sum_e V_i[e] w[e] for i < k (V_i = V + i * ldv); partial >= 512 * k
+// out[i] = sum_e V_i[e] w[e] for i < k (V_i = V + i * ldv), and out[k] = w.w
+// if with_self; partial holds 65536 doubles.
 hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
-                      double* partial, double* out, hipStream_t s);
+                      double* partial, double* out, hipStream_t s, int with_self = 0);
 // y += alpha * sum_i c[i] X_i  (c on device)
 hipError_t k_multiaxpy(double* y, const double* X, int64_t ldx, int k, const double* c,
                        double alpha, int64_t n, hipStream_t s);

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "iss_internal.h"
 
@@ -60,13 +61,13 @@ constexpr int BX = 64, BY = 4;   // 256-thread workgroups: 64 along x, 4 rows
 // Interior vertex (1..n-1 per axis) of a bulk kernel; `step` > 1 walks one
 // colour class along x.  Returns false for threads past the row end.
 template <int D>
-__device__ __forceinline__ bool interior_vertex(const LevelView& L, int colour, int step,
+__device__ __forceinline__ bool interior_vertex(const LevelView& L, int colour, int step, int64_t bid,
                                                 int& i, int& j, int& k) {
     const int m = L.n - 1;                       // interior points per axis
     const int cnt = (step == 1) ? m : (m + step - 1) / step;
     const int gx = (cnt + BX - 1) / BX, gy = (m + BY - 1) / BY;
     const int64_t nb = (int64_t)gx * gy * (D == 3 ? m : 1);
-    const int64_t b = xcd_remap(blockIdx.x, nb);
+    const int64_t b = xcd_remap(bid, nb);
     const int bx = (int)(b % gx);
     const int64_t r = b / gx;
     const int by = (int)(r % gy);
@@ -166,13 +167,22 @@ struct RowAcc {
     C cjj;            // point diagonal of sum_T (1/mu_T) C_T
 };
 
-template <int D, int F, bool VEL, bool PRES, bool WANT_D, bool WANT_DELTA, typename T, typename C>
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(fn);
+    }
+}
+
+// The slot and vertex loops are unrolled at compile time, so every index
+// into the preloaded footprint arrays is a constant (registers, no scratch).
+template <int D, int F, bool VEL, bool PRES, bool WANT_D, bool WANT_DELTA, typename C>
 __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
                                              const C (&U)[D][KuhnTables<D>::NB],
                                              const C (&P)[KuhnTables<D>::NB],
                                              const C (&Dl)[KuhnTables<D>::NB],
                                              RowAcc<D, F, VEL, PRES, C>& r) {
-    constexpr auto& TT = Kuhn<D>::T;
     constexpr int NS = KuhnTables<D>::NS;
     const auto& E = ETab<D, C>::get();
 #pragma unroll
@@ -183,19 +193,18 @@ __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
     }
     r.bdiv = 0; r.cp = 0; r.cd = 0; r.cjj = 0;
     const uint8_t* eph = L.spec_eph + s * NS;
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) {
+    static_for<0, NS>([&](auto slc) {
+        constexpr int sl = decltype(slc)::value;
         const int ph = eph[sl];
-        if (ph == OUTSIDE) continue;
-        constexpr int dummy = 0; (void)dummy;
-        const int ty = TT.slot_type[sl];
-        const int a = TT.slot_loc[sl];
+        if (ph == OUTSIDE) return;
+        constexpr int ty = Kuhn<D>::T.slot_type[sl];
+        constexpr int a = Kuhn<D>::T.slot_loc[sl];
         const C mu = Prec<C>::mu(L, ph);
         const C imu = Prec<C>::imu(L, ph);
-#pragma unroll
-        for (int bb = 0; bb <= D; ++bb) {
-            const int o = TT.slot_nb[sl][bb];
-            if (VEL) {
+        static_for<0, D + 1>([&](auto bc) {
+            constexpr int bb = decltype(bc)::value;
+            constexpr int o = Kuhn<D>::T.slot_nb[sl][bb];
+            if constexpr (VEL) {
 #pragma unroll
                 for (int l = 0; l < D; ++l) {
                     C acc = 0;
@@ -204,7 +213,7 @@ __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
                     r.au[l] += mu * acc;
                     r.abt[l] += E.Bel[ty][bb][a * D + l] * P[o];
                 }
-                if (WANT_D && bb == a) {
+                if constexpr (WANT_D && bb == a) {
 #pragma unroll
                     for (int l = 0; l < D; ++l)
 #pragma unroll
@@ -212,29 +221,29 @@ __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
                             r.Dm[l][k] += mu * E.Avis[F][ty][a * D + l][a * D + k];
                 }
             }
-            if (PRES) {
+            if constexpr (PRES) {
                 C acc = 0;
 #pragma unroll
                 for (int k = 0; k < D; ++k) acc += E.Bel[ty][a][bb * D + k] * U[k][o];
                 r.bdiv += acc;
                 r.cp += imu * E.Cel[ty][a][bb] * P[o];
-                if (WANT_DELTA) r.cd += imu * E.Cel[ty][a][bb] * Dl[o];
-                if (WANT_D && bb == a) r.cjj += imu * E.Cel[ty][a][a];
+                if constexpr (WANT_DELTA) r.cd += imu * E.Cel[ty][a][bb] * Dl[o];
+                if constexpr (WANT_D && bb == a) r.cjj += imu * E.Cel[ty][a][a];
             }
-        }
-    }
+        });
+    });
 }
 
 // ----------------------------------------------------------------------------
 // operator apply / residual
 
 template <int D, int F, int BLK, int MODE, typename T>
-__global__ __launch_bounds__(256) void k_apply_bulk(LevelView L, const T* __restrict__ x,
-                                                    const T* __restrict__ b, T* __restrict__ y) {
+__device__ __forceinline__ void apply_bulk_body(const LevelView& L, int64_t bid, const T* __restrict__ x,
+                                                const T* __restrict__ b, T* __restrict__ y) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
     int i, j, k;
-    if (!interior_vertex<D>(L, 0, 1, i, j, k)) return;
+    if (!interior_vertex<D>(L, 0, 1, bid, i, j, k)) return;
     const int64_t v = i + j * L.sy + k * L.sz;
     const int ph = L.vphase[v];
     if (ph == SPECIAL) return;
@@ -310,22 +319,20 @@ __global__ __launch_bounds__(256) void k_apply_bulk(LevelView L, const T* __rest
 }
 
 template <int D, int F, int BLK, int MODE, typename T>
-__global__ __launch_bounds__(256) void k_apply_special(LevelView L, const T* __restrict__ x,
-                                                       const T* __restrict__ b,
-                                                       T* __restrict__ y) {
+__device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s, const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ y) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= L.spec_off[D + 1]) return;
     const int64_t v = L.spec[s];
     int ijk[3];
     vertex_ijk<D>(L, v, ijk);
     const bool bnd = on_boundary<D>(L, ijk);
-    C U[D][NB], P[1][NB], Dl[NB];
+    C U[D][NB], P[1][NB];
     load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
     load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
     RowAcc<D, F, true, BLK == BLOCK_FULL, C> r;
-    element_rows<D, F, true, BLK == BLOCK_FULL, false, false, T, C>(L, s, U, P[0], Dl, r);
+    element_rows<D, F, true, BLK == BLOCK_FULL, false, false, C>(L, s, U, P[0], P[0], r);
     C out[D + 1];
 #pragma unroll
     for (int l = 0; l < D; ++l)
@@ -341,6 +348,21 @@ __global__ __launch_bounds__(256) void k_apply_special(LevelView L, const T* __r
             y[e] = (T)out[f];
         }
     }
+}
+
+// Applies: one launch over the interior isoviscous vertices (bulk
+// stencils), one over the special-vertex list (element loops).
+
+template <int D, int F, int BLK, int MODE, typename T>
+__global__ __launch_bounds__(256) void k_apply_bulk(LevelView L, const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y) {
+    apply_bulk_body<D, F, BLK, MODE, T>(L, blockIdx.x, x, b, y);
+}
+
+template <int D, int F, int BLK, int MODE, typename T>
+__global__ __launch_bounds__(256) void k_apply_special(LevelView L, const T* __restrict__ x,
+                                                       const T* __restrict__ b, T* __restrict__ y) {
+    apply_special_body<D, F, BLK, MODE, T>(L, (int64_t)blockIdx.x * 256 + threadIdx.x, x, b, y);
 }
 
 // ----------------------------------------------------------------------------
@@ -369,28 +391,41 @@ __device__ __forceinline__ void block_gs_update(C (&r)[D], const C (&Dm)[D][D], 
     }
 }
 
-template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_bulk(LevelView L, int colour, T* __restrict__ x,
-                                                     const T* __restrict__ b) {
+// g = f - B^T p on interior isoviscous vertices (p is fixed during the
+// velocity sweep, so the coupling term is formed once per sweep).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_vel_rhs_bulk(LevelView L, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ g) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
     int i, j, k;
-    if (!interior_vertex<D>(L, colour, D + 1, i, j, k)) return;
+    if (!interior_vertex<D>(L, 0, 1, blockIdx.x, i, j, k)) return;
     const int64_t v = i + j * L.sy + k * L.sz;
-    const int ph = L.vphase[v];
-    if (ph == SPECIAL) return;
+    if (L.vphase[v] == SPECIAL) return;
     const auto& E = ETab<D, C>::get();
-    const C smu = Prec<C>::mu(L, ph) * (C)L.sA;
     C P[1][NB];
     load_interior<D, 1, T, C>(L, x, v, D, P);
-    C rhs[D];
 #pragma unroll
     for (int l = 0; l < D; ++l) {
         C acc = 0;
 #pragma unroll
         for (int o = 1; o < NB; ++o) acc += E.Sbt[l][o] * P[0][o];
-        rhs[l] = (C)b[(int64_t)l * L.N + v] - (C)L.sB * acc;
+        g[(int64_t)l * L.N + v] = (T)((C)b[(int64_t)l * L.N + v] - (C)L.sB * acc);
     }
+}
+
+template <int D, int F, bool BWD, typename T>
+__device__ __forceinline__ void gs_vel_bulk_body(const LevelView& L, int64_t bid, int colour, T* __restrict__ x,
+                                                 const T* __restrict__ g) {
+    using C = T;
+    constexpr int NB = KuhnTables<D>::NB;
+    int i, j, k;
+    if (!interior_vertex<D>(L, colour, D + 1, bid, i, j, k)) return;
+    const int64_t v = i + j * L.sy + k * L.sz;
+    const int ph = L.vphase[v];
+    if (ph == SPECIAL) return;
+    const auto& E = ETab<D, C>::get();
+    const C smu = Prec<C>::mu(L, ph) * (C)L.sA;
     if (F == FORM_STRAIN) {
         C U[D][NB];
         load_interior<D, D, T, C>(L, x, v, 0, U);
@@ -404,13 +439,13 @@ __global__ __launch_bounds__(256) void k_gs_vel_bulk(LevelView L, int colour, T*
                 for (int o = 0; o < NB; ++o) acc += E.Svis[1][l][kk][o] * U[kk][o];
                 Dm[l][kk] = smu * E.Svis[1][l][kk][0];
             }
-            r[l] = rhs[l] - smu * acc;
+            r[l] = (C)g[(int64_t)l * L.N + v] - smu * acc;
         }
         block_gs_update<D, F, BWD, C>(r, Dm, du);
 #pragma unroll
         for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)(U[l][0] + du[l]);
     } else {
-        // decoupled components: u_l = (rhs_l / (mu sA) - sum_nb w u_l) / w_0
+        // decoupled components: u_l = (g_l / (mu sA) - sum_nb w u_l) / w_0
 #pragma unroll
         for (int l = 0; l < D; ++l) {
             T* ul = x + (int64_t)l * L.N + v;
@@ -418,28 +453,26 @@ __global__ __launch_bounds__(256) void k_gs_vel_bulk(LevelView L, int colour, T*
 #pragma unroll
             for (int o = 1; o <= 2 * D; ++o) acc += E.Svis[0][l][l][o] * (C)ul[nb_lin<D>(L, o)];
             const C w0 = smu * E.Svis[0][l][l][0];
-            ul[0] = (T)((rhs[l] - smu * acc) / w0);
+            ul[0] = (T)(((C)g[(int64_t)l * L.N + v] - smu * acc) / w0);
         }
     }
 }
 
 template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_special(LevelView L, int colour,
-                                                        T* __restrict__ x,
-                                                        const T* __restrict__ b) {
+__device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int64_t s, int colour,
+                                                    T* __restrict__ x, const T* __restrict__ b) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t s = L.spec_off[colour] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= L.spec_off[colour + 1]) return;
     const int64_t v = L.spec[s];
     int ijk[3];
     vertex_ijk<D>(L, v, ijk);
     if (on_boundary<D>(L, ijk)) return;          // Dirichlet velocity
-    C U[D][NB], P[1][NB], Dl[NB];
+    C U[D][NB], P[1][NB];
     load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
     load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
     RowAcc<D, F, true, false, C> r;
-    element_rows<D, F, true, false, true, false, T, C>(L, s, U, P[0], Dl, r);
+    element_rows<D, F, true, false, true, false, C>(L, s, U, P[0], P[0], r);
     C res[D], Dm[D][D], du[D];
 #pragma unroll
     for (int l = 0; l < D; ++l) {
@@ -449,20 +482,36 @@ __global__ __launch_bounds__(256) void k_gs_vel_special(LevelView L, int colour,
     }
     block_gs_update<D, F, BWD, C>(res, Dm, du);
 #pragma unroll
-    for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)(U[l][0] + du[l]);
+    for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)((C)x[(int64_t)l * L.N + v] + du[l]);
 }
 
 // pressure: one colour phase of the forward Gauss-Seidel sweep on
 // C delta = B u - C p - g started from delta = 0.
+// One colour phase of the symmetric velocity sweep: the bulk launch reads
+// g = f - B^T p, the special launch forms its rows from the incident
+// elements.
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_bulk(LevelView L, int colour, T* __restrict__ x,
+                                                     const T* __restrict__ g) {
+    gs_vel_bulk_body<D, F, BWD, T>(L, blockIdx.x, colour, x, g);
+}
+
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_special(LevelView L, int colour, T* __restrict__ x,
+                                                        const T* __restrict__ b) {
+    gs_vel_special_body<D, F, BWD, T>(L, L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x,
+                                      colour, x, b);
+}
+
+// s = B u - C p - g on interior isoviscous vertices (u and p are fixed
+// during the pressure sweep).
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_bulk(LevelView L, int colour,
-                                                   const T* __restrict__ x,
-                                                   const T* __restrict__ b,
-                                                   T* __restrict__ delta) {
+__global__ __launch_bounds__(256) void k_p_rhs_bulk(LevelView L, const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ sres) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
     int i, j, k;
-    if (!interior_vertex<D>(L, colour, D + 1, i, j, k)) return;
+    if (!interior_vertex<D>(L, 0, 1, blockIdx.x, i, j, k)) return;
     const int64_t v = i + j * L.sy + k * L.sz;
     const int ph = L.vphase[v];
     if (ph == SPECIAL) return;
@@ -475,25 +524,36 @@ __global__ __launch_bounds__(256) void k_gs_p_bulk(LevelView L, int colour,
     for (int kk = 0; kk < D; ++kk)
 #pragma unroll
         for (int o = 1; o < NB; ++o) dv += E.Sdiv[kk][o] * U[kk][o];
-    const C sci = (C)L.sC * Prec<C>::imu(L, ph);
-    C cp = E.Sc[0] * P[0][0], cd = 0;
+    C cp = E.Sc[0] * P[0][0];
 #pragma unroll
-    for (int o = 1; o <= 2 * D; ++o) {
-        cp += E.Sc[o] * P[0][o];
-        cd += E.Sc[o] * (C)delta[v + nb_lin<D>(L, o)];
-    }
-    const C sres = (C)L.sB * dv - sci * cp - (C)b[(int64_t)D * L.N + v];
-    delta[v] = (T)((sres - sci * cd) / (sci * E.Sc[0]));
+    for (int o = 1; o <= 2 * D; ++o) cp += E.Sc[o] * P[0][o];
+    const C sci = (C)L.sC * Prec<C>::imu(L, ph);
+    sres[v] = (T)((C)L.sB * dv - sci * cp - (C)b[(int64_t)D * L.N + v]);
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_special(LevelView L, int colour,
-                                                      const T* __restrict__ x,
-                                                      const T* __restrict__ b,
-                                                      T* __restrict__ delta) {
+__device__ __forceinline__ void gs_p_bulk_body(const LevelView& L, int64_t bid, int colour,
+                                               const T* __restrict__ sres, T* __restrict__ delta) {
+    using C = T;
+    int i, j, k;
+    if (!interior_vertex<D>(L, colour, D + 1, bid, i, j, k)) return;
+    const int64_t v = i + j * L.sy + k * L.sz;
+    const int ph = L.vphase[v];
+    if (ph == SPECIAL) return;
+    const auto& E = ETab<D, C>::get();
+    C cd = 0;
+#pragma unroll
+    for (int o = 1; o <= 2 * D; ++o) cd += E.Sc[o] * (C)delta[v + nb_lin<D>(L, o)];
+    const C sci = (C)L.sC * Prec<C>::imu(L, ph);
+    delta[v] = (T)(((C)sres[v] - sci * cd) / (sci * E.Sc[0]));
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void gs_p_special_body(const LevelView& L, int64_t s, int colour,
+                                                  const T* __restrict__ x, const T* __restrict__ b,
+                                                  T* __restrict__ delta) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t s = L.spec_off[colour] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= L.spec_off[colour + 1]) return;
     const int64_t v = L.spec[s];
     int ijk[3];
@@ -503,9 +563,23 @@ __global__ __launch_bounds__(256) void k_gs_p_special(LevelView L, int colour,
     load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
     load_guarded<D, 1, T, C>(L, delta, v, ijk, 0, Dl);
     RowAcc<D, FORM_GRADIENT, false, true, C> r;
-    element_rows<D, FORM_GRADIENT, false, true, true, true, T, C>(L, s, U, P[0], Dl[0], r);
+    element_rows<D, FORM_GRADIENT, false, true, true, true, C>(L, s, U, P[0], Dl[0], r);
     const C sres = (C)L.sB * r.bdiv - (C)L.sC * r.cp - (C)b[(int64_t)D * L.N + v];
     delta[v] = (T)((sres - (C)L.sC * r.cd) / ((C)L.sC * r.cjj));
+}
+
+// One colour phase of the pressure sweep (bulk and special launches).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_bulk(LevelView L, int colour, const T* __restrict__ sres,
+                                                   T* __restrict__ delta) {
+    gs_p_bulk_body<D, T>(L, blockIdx.x, colour, sres, delta);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_special(LevelView L, int colour, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ delta) {
+    gs_p_special_body<D, T>(L, L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x, colour, x, b,
+                            delta);
 }
 
 template <typename T>
@@ -629,18 +703,43 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
     }
 }
 
-// multi-dot: partial[i * gridDim + blk] = sum over block range of V_i w
+// multi-dot: partial[i * gridDim.x + blk] = sum over the block's elements of
+// V_i w, 16 vectors per workgroup row (blockIdx.y) so w is read once per
+// 16 dot products; vector k (i == k) is w itself when with_self is set.
+constexpr int MD_TILE = 16;
 __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restrict__ V, int64_t ldv,
                                                           int k, const double* __restrict__ w,
-                                                          int64_t n, double* __restrict__ partial) {
-    __shared__ double sh[4];
-    for (int i = 0; i < k; ++i) {
-        const double* vi = V + (int64_t)i * ldv;
-        double acc = 0;
-        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-            acc += vi[e] * w[e];
-        const double s = block_sum<256>(acc, sh);
-        if (threadIdx.x == 0) partial[(int64_t)i * gridDim.x + blockIdx.x] = s;
+                                                          int64_t n, double* __restrict__ partial,
+                                                          int with_self) {
+    __shared__ double sh[MD_TILE][4];
+    const int i0 = blockIdx.y * MD_TILE;
+    const int kk = k + with_self;
+    const int cnt = min(MD_TILE, kk - i0);
+    double acc[MD_TILE];
+#pragma unroll
+    for (int q = 0; q < MD_TILE; ++q) acc[q] = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double we = w[e];
+#pragma unroll
+        for (int q = 0; q < MD_TILE; ++q) {
+            if (q < cnt) {
+                const int i = i0 + q;
+                const double vi = (i < k) ? V[(int64_t)i * ldv + e] : we;
+                acc[q] += vi * we;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < MD_TILE; ++q) {
+        double v = acc[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) sh[q][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        const int q = threadIdx.x;
+        partial[(int64_t)(i0 + q) * gridDim.x + blockIdx.x] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
     }
 }
 
@@ -708,7 +807,7 @@ __global__ __launch_bounds__(256) void k_buoyancy_bulk(LevelView L, const uint8_
                                                        double rho, double vol, double* __restrict__ b) {
     constexpr int NS = KuhnTables<D>::NS;
     int i, j, k;
-    if (!interior_vertex<D>(L, 0, 1, i, j, k)) return;
+    if (!interior_vertex<D>(L, 0, 1, blockIdx.x, i, j, k)) return;
     const int64_t v = i + j * L.sy + k * L.sz;
     const int ph = L.vphase[v];
     if (ph == SPECIAL) return;
@@ -753,15 +852,18 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
     return hipMemcpyToSymbol(HIP_SYMBOL(g_e2f), t32, bytes32);
 }
 
+static inline int64_t special_blocks(int64_t ns) { return (ns + 255) / 256; }
+
 template <int D, int F, int BLK, int MODE, typename T>
 static hipError_t apply_t(const LevelView& L, const T* x, const T* b, T* y, hipStream_t s) {
     const int64_t nb = interior_blocks<D>(L.n, 1);
     if (nb > 0)
         hipLaunchKernelGGL((k_apply_bulk<D, F, BLK, MODE, T>), dim3((unsigned)nb), dim3(BX, BY), 0, s,
                            L, x, b, y);
-    const int64_t ns = L.spec_off[D + 1];
+    const int64_t ns = special_blocks(L.spec_off[D + 1]);
     if (ns > 0)
-        hipLaunchKernelGGL((k_apply_special<D, F, BLK, MODE, T>), grid1(ns), dim3(256), 0, s, L, x, b, y);
+        hipLaunchKernelGGL((k_apply_special<D, F, BLK, MODE, T>), dim3((unsigned)ns), dim3(256), 0, s,
+                           L, x, b, y);
     return hipGetLastError();
 }
 
@@ -788,35 +890,42 @@ hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, 
 }
 
 template <int D, int F, typename T>
-static hipError_t smooth_t(const LevelView& L, double omega, T* x, const T* b, T* delta, hipStream_t s) {
+static hipError_t smooth_t(const LevelView& L, double omega, T* x, const T* b, T* work, hipStream_t s) {
+    const int64_t nb1 = interior_blocks<D>(L.n, 1);
     const int64_t nbc = interior_blocks<D>(L.n, D + 1);
+    T* g = work;                                   // D fields: f - B^T p
+    T* sres = work;                                // field 0: B u - C p - g
+    T* delta = work + (int64_t)D * L.N;            // field D
     // velocity: forward colours 0..D, then backward colours D..0
+    if (nb1 > 0)
+        hipLaunchKernelGGL((k_vel_rhs_bulk<D, T>), dim3((unsigned)nb1), dim3(BX, BY), 0, s, L, x, b, g);
     for (int pass = 0; pass < 2; ++pass) {
         for (int cc = 0; cc <= D; ++cc) {
             const int c = pass == 0 ? cc : D - cc;
-            if (nbc > 0) {
-                if (pass == 0)
-                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, false, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, b);
-                else
-                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, true, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, b);
-            }
-            const int64_t ns = L.spec_off[c + 1] - L.spec_off[c];
-            if (ns > 0) {
-                if (pass == 0)
-                    hipLaunchKernelGGL((k_gs_vel_special<D, F, false, T>), grid1(ns), dim3(256), 0, s, L, c, x, b);
-                else
-                    hipLaunchKernelGGL((k_gs_vel_special<D, F, true, T>), grid1(ns), dim3(256), 0, s, L, c, x, b);
+            const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
+            if (pass == 0) {
+                if (nbc > 0)
+                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, false, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, g);
+                if (ns > 0)
+                    hipLaunchKernelGGL((k_gs_vel_special<D, F, false, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, x, b);
+            } else {
+                if (nbc > 0)
+                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, true, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, g);
+                if (ns > 0)
+                    hipLaunchKernelGGL((k_gs_vel_special<D, F, true, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, x, b);
             }
         }
     }
     // pressure: delta = 0, forward colour sweep on C, p += omega delta
     hipLaunchKernelGGL((k_fill_t<T>), grid1(L.N), dim3(256), 0, s, delta, L.N, (T)0);
+    if (nb1 > 0)
+        hipLaunchKernelGGL((k_p_rhs_bulk<D, T>), dim3((unsigned)nb1), dim3(BX, BY), 0, s, L, x, b, sres);
     for (int c = 0; c <= D; ++c) {
         if (nbc > 0)
-            hipLaunchKernelGGL((k_gs_p_bulk<D, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, b, delta);
-        const int64_t ns = L.spec_off[c + 1] - L.spec_off[c];
+            hipLaunchKernelGGL((k_gs_p_bulk<D, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, sres, delta);
+        const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
         if (ns > 0)
-            hipLaunchKernelGGL((k_gs_p_special<D, T>), grid1(ns), dim3(256), 0, s, L, c, x, b, delta);
+            hipLaunchKernelGGL((k_gs_p_special<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, x, b, delta);
     }
     hipLaunchKernelGGL((k_axpy_field<T>), grid1(L.N), dim3(256), 0, s, x + (int64_t)D * L.N, delta,
                        (T)omega, L.N);
@@ -824,22 +933,22 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* x, const T* b, T
 }
 
 template <int D, typename T>
-static hipError_t smooth_d(const LevelView& L, int form, double omega, T* x, const T* b, T* delta,
+static hipError_t smooth_d(const LevelView& L, int form, double omega, T* x, const T* b, T* work,
                            hipStream_t s) {
-    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, x, b, delta, s);
-    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, x, b, delta, s);
-    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, x, b, delta, s);
+    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, x, b, work, s);
+    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, x, b, work, s);
+    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, x, b, work, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* x, const void* b,
-                         void* delta, hipStream_t s) {
+                         void* work, hipStream_t s) {
     if (prec == PREC_F64) {
-        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)x, (const double*)b, (double*)delta, s);
-        return smooth_d<2, double>(L, form, omega, (double*)x, (const double*)b, (double*)delta, s);
+        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)x, (const double*)b, (double*)work, s);
+        return smooth_d<2, double>(L, form, omega, (double*)x, (const double*)b, (double*)work, s);
     }
-    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)x, (const float*)b, (float*)delta, s);
-    return smooth_d<2, float>(L, form, omega, (float*)x, (const float*)b, (float*)delta, s);
+    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)x, (const float*)b, (float*)work, s);
+    return smooth_d<2, float>(L, form, omega, (float*)x, (const float*)b, (float*)work, s);
 }
 
 hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf, void* rc,
@@ -898,12 +1007,14 @@ hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* par
 }
 
 hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial,
-                      double* out, hipStream_t s) {
-    // partial holds 1024 * 64 doubles: at most 65536 / k blocks
-    const int64_t cap = std::max<int64_t>(1, 65536 / std::max(1, k));
-    const int nblk = (int)std::min<int64_t>(std::min<int64_t>(512, cap), std::max<int64_t>(1, (n + 255) / 256));
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(256), 0, s, V, ldv, k, w, n, partial);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, k, out);
+                      double* out, hipStream_t s, int with_self) {
+    // partial holds 1024 * 64 doubles: at most 65536 / (k + 1) blocks per vector
+    const int kk = k + with_self;
+    const int64_t cap = std::max<int64_t>(1, 65536 / std::max(1, kk));
+    const int nblk = (int)std::min<int64_t>(std::min<int64_t>(1024, cap), std::max<int64_t>(1, (n + 255) / 256));
+    const int tiles = (kk + MD_TILE - 1) / MD_TILE;
+    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, tiles), dim3(256), 0, s, V, ldv, k, w, n, partial, with_self);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, kk, out);
     return hipGetLastError();
 }
 

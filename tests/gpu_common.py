@@ -35,7 +35,10 @@ def small_workload(name, levels, macro=None, seed=0):
 
 
 def gpu_problem(w, **kw):
+    """Library problem for a workload; coarse levels use the centroid rule
+    (the oracle hierarchy's rediscretisation) unless stated."""
     from paper_1604_07994_amd import Problem
+    kw.setdefault("coarse_mu", "centroid")
     return Problem.from_workload(w, **kw)
 
 
