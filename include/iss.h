@@ -109,6 +109,8 @@ typedef struct {
     double seconds;       /* wall time of the solve (host clock, synced)    */
     int history_len;      /* entries written to history                     */
     double* history;      /* optional host array (maxit+1) of relres, or 0  */
+    int net_accepted;     /* band corrections kept by the safeguard          */
+    int net_rejected;     /* band corrections dropped (plain V-cycle used)   */
 } iss_solve_info;
 
 /* Fill *opt with the defaults above.  Returns ISS_OK. */
@@ -194,6 +196,61 @@ int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double
 /* Euclidean dot product of two FP64 device vectors of length n. */
 int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double* out,
             iss_stream_t stream);
+
+/* ---- learned interface-band correction (3D) --------------------------------
+ * Not part of the paper: a small convolutional network that corrects the
+ * V-cycle output on the band of vertices within Chebyshev distance 2 of an
+ * interface vertex (finest level), where the plain smoother degrades.
+ * Network: three 3x3x3 convolutions 8 -> 16 -> 16 -> 4 channels with ReLU,
+ * no biases, zero padding off the band; BF16 operands with FP32
+ * accumulation (MFMA).  Input channels per band vertex: r_1..r_3 / s_u,
+ * r_p / s_p, log10(max incident viscosity) / 4, interface flag, 0, 0, where
+ * s_u and s_p are the band RMS of the velocity and pressure residual.
+ * Outputs are in Jacobi units: channel 0..2 times s_u / (6 mu h) and
+ * channel 3 times s_p mu / (6 beta h^3), mu = largest incident viscosity,
+ * form the correction; training targets are errors in the same units.
+ * Parameters: FP32, flat [W1 | W2 | W3], W[c_out][c_in][tap], tap =
+ * (dx+1) + 3 (dy+1) + 9 (dz+1); 12096 values. */
+typedef struct iss_net iss_net;
+
+/* Create the network state for the finest level of p (band, buffers). */
+int iss_net_create(iss_problem* p, iss_net** out);
+void iss_net_destroy(iss_net* net);
+/* Band size M and parameter count. */
+int iss_net_info(const iss_net* net, int64_t* band_size, int64_t* num_params);
+/* Band vertex ids (ascending) into host array band (M entries). */
+int iss_net_band(const iss_net* net, int32_t* band);
+/* Load FP32 parameters from device memory (converted to BF16 fragments). */
+int iss_net_set_weights(iss_net* net, const float* w, iss_stream_t stream);
+/* Build the input from an FP64 residual r ((d+1) N, device); scales, if
+ * non-NULL, receives (s_u, s_p) on the host (synchronises). */
+int iss_net_features(iss_net* net, const double* r, double* scales, iss_stream_t stream);
+/* Run the network on the current input; y (device, M x 4 FP32, band order)
+ * receives the output if non-NULL. */
+int iss_net_forward(iss_net* net, float* y, iss_stream_t stream);
+/* Training targets from an error vector e ((d+1) N, FP64, device): t (M x 4
+ * FP32) = e on the band in the output units above (current scales). */
+int iss_net_targets(iss_net* net, const double* e, float* t, iss_stream_t stream);
+/* Gradient with respect to the parameters (grad: device FP32, overwritten)
+ * of the last forward pass.  With t non-NULL the loss is the mean squared
+ * error against t (value to *loss on the host if non-NULL; synchronises);
+ * with t NULL the output gradient set by iss_net_output_grad is used. */
+int iss_net_backward(iss_net* net, const float* t, float* grad, double* loss, iss_stream_t stream);
+/* The correction c ((d+1) N FP64, device, overwritten; zero off the band)
+ * given by the last forward pass. */
+int iss_net_correction(iss_net* net, double* c, iss_stream_t stream);
+/* Set the output gradient dL/dy of the last forward pass from a gradient
+ * with respect to the correction, dL/dc = factor * g (g: (d+1) N FP64,
+ * device). */
+int iss_net_output_grad(iss_net* net, const double* g, double factor, iss_stream_t stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected, step >= 1) on
+ * n FP32 parameters w with moments m, v and gradient g (device). */
+int iss_adam_step(int64_t n, float* w, float* m, float* v, const float* g, float lr, int step,
+                  iss_stream_t stream);
+/* Attach a network to iss_solve (NULL detaches).  With a network attached
+ * the preconditioner is z = V(r) + c, c = the band correction computed from
+ * r - K V(r), kept only if it lowers that residual's norm. */
+int iss_problem_set_net(iss_problem* p, iss_net* net);
 
 /* Message describing the last error on the calling thread. */
 const char* iss_last_error(void);

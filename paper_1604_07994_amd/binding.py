@@ -38,13 +38,17 @@ class Options(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("relres", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("history_len", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)),
+                ("net_accepted", ctypes.c_int), ("net_rejected", ctypes.c_int)]
 
 
 EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "iss_num_vertices",
            "iss_vertex_class", "iss_rhs_buoyancy", "iss_apply", "iss_residual", "iss_smooth",
            "iss_restrict", "iss_prolong_add", "iss_coarse_solve", "iss_vcycle", "iss_solve",
-           "iss_dot", "iss_last_error"]
+           "iss_dot", "iss_last_error", "iss_net_create", "iss_net_destroy", "iss_net_info",
+           "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
+           "iss_net_targets", "iss_net_backward", "iss_adam_step", "iss_problem_set_net",
+           "iss_net_correction", "iss_net_output_grad"]
 
 
 def lib():
@@ -79,6 +83,20 @@ def lib():
     L.iss_vcycle.argtypes = [vp, cint, cint, vp, vp, vp]
     L.iss_solve.argtypes = [vp, cint, cint, cdbl, cint, vp, vp, ctypes.POINTER(SolveInfo), vp]
     L.iss_dot.argtypes = [vp, vp, vp, i64, ctypes.POINTER(cdbl), vp]
+    L.iss_net_create.argtypes = [vp, ctypes.POINTER(vp)]
+    L.iss_net_destroy.argtypes = [vp]
+    L.iss_net_destroy.restype = None
+    L.iss_net_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.iss_net_band.argtypes = [vp, vp]
+    L.iss_net_set_weights.argtypes = [vp, vp, vp]
+    L.iss_net_features.argtypes = [vp, vp, ctypes.POINTER(cdbl), vp]
+    L.iss_net_forward.argtypes = [vp, vp, vp]
+    L.iss_net_targets.argtypes = [vp, vp, vp, vp]
+    L.iss_net_backward.argtypes = [vp, vp, vp, ctypes.POINTER(cdbl), vp]
+    L.iss_adam_step.argtypes = [i64, vp, vp, vp, vp, ctypes.c_float, cint, vp]
+    L.iss_problem_set_net.argtypes = [vp, vp]
+    L.iss_net_correction.argtypes = [vp, vp, vp]
+    L.iss_net_output_grad.argtypes = [vp, vp, cdbl, vp]
     _lib = L
     return L
 
@@ -233,14 +251,15 @@ class Problem:
     def solve(self, form, x, b, prec="fp64", rtol=1e-8, maxit=200, raise_on_fail=True):
         import torch
         hist = (ctypes.c_double * (maxit + 1))()
-        info = SolveInfo(0, 0.0, 0.0, 0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)))
+        info = SolveInfo(0, 0.0, 0.0, 0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), 0, 0)
         rc = lib().iss_solve(self._h, FORMS[form], PREC_F64 if prec == "fp64" else PREC_F32, rtol,
                              maxit, self._vec(x, self.levels, torch.float64),
                              self._vec(b, self.levels, torch.float64), ctypes.byref(info), _stream())
         if rc != 0 and raise_on_fail:
             _check(rc)
         return {"status": rc, "iterations": info.iterations, "relres": info.relres,
-                "seconds": info.seconds, "history": [hist[i] for i in range(info.history_len)]}
+                "seconds": info.seconds, "history": [hist[i] for i in range(info.history_len)],
+                "net_accepted": info.net_accepted, "net_rejected": info.net_rejected}
 
     def dot(self, a, b):
         import torch
@@ -253,3 +272,76 @@ class Problem:
         _check(lib().iss_dot(self._h, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
                              a.numel(), ctypes.byref(out), _stream()))
         return out.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class BandNet:
+    """The learned band correction of a (3D) Problem; weights are FP32 torch
+    tensors on the device, flat [W1 | W2 | W3]."""
+
+    def __init__(self, problem):
+        h = ctypes.c_void_p()
+        _check(lib().iss_net_create(problem._h, ctypes.byref(h)))
+        self._h = h
+        self.problem = problem
+        m, npar = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().iss_net_info(h, ctypes.byref(m), ctypes.byref(npar)))
+        self.band_size, self.num_params = m.value, npar.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iss_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def band(self):
+        out = np.zeros(self.band_size, dtype=np.int32)
+        _check(lib().iss_net_band(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_weights(self, w):
+        _check(lib().iss_net_set_weights(self._h, _ptr(w), _stream()))
+
+    def features(self, r):
+        sc = (ctypes.c_double * 2)()
+        _check(lib().iss_net_features(self._h, _ptr(r), sc, _stream()))
+        return sc[0], sc[1]
+
+    def forward(self, y=None):
+        _check(lib().iss_net_forward(self._h, _ptr(y) if y is not None else None, _stream()))
+        return y
+
+    def targets(self, e, t):
+        _check(lib().iss_net_targets(self._h, _ptr(e), _ptr(t), _stream()))
+        return t
+
+    def backward(self, t, grad):
+        """MSE against targets t, or (t None) the output gradient set by
+        output_grad(); returns the MSE value or None."""
+        loss = ctypes.c_double()
+        _check(lib().iss_net_backward(self._h, _ptr(t) if t is not None else None, _ptr(grad),
+                                      ctypes.byref(loss) if t is not None else None, _stream()))
+        return loss.value if t is not None else None
+
+    def correction(self, c):
+        _check(lib().iss_net_correction(self._h, _ptr(c), _stream()))
+        return c
+
+    def output_grad(self, g, factor=1.0):
+        """dL/dc = factor * g."""
+        _check(lib().iss_net_output_grad(self._h, _ptr(g), factor, _stream()))
+
+    def attach(self, on=True):
+        _check(lib().iss_problem_set_net(self.problem._h, self._h if on else None))
+
+
+def adam_step(w, m, v, g, lr, step):
+    _check(lib().iss_adam_step(w.numel(), _ptr(w), _ptr(m), _ptr(v), _ptr(g), lr, step, _stream()))

@@ -158,6 +158,9 @@ struct Level {
     std::vector<uint8_t> elem_phase;// per element (cell * NT + type)
     std::vector<double> mu_tab, imu_tab;     // viscosity and 1/viscosity per phase
     std::vector<double> emu, eimu;  // per element averages (setup only)
+    std::vector<uint8_t> h_vphase;  // finest level: host copy of the phase bytes
+    std::vector<int32_t> h_spec;    // finest level: special vertices
+    std::vector<uint8_t> h_eph;     // finest level: their slot phases
     double* d_mu64 = nullptr;
     double* d_imu64 = nullptr;
     float* d_mu32 = nullptr;
@@ -205,7 +208,14 @@ struct iss_problem {
     uint8_t* d_flag = nullptr;      // 256 buoyancy flags
     double* h_pinned = nullptr;     // 8192 doubles of pinned host memory
     int64_t reorth_count = 0;       // second Gram-Schmidt passes (diagnostics)
+    iss_net* net = nullptr;         // attached band correction (not owned)
+    int net_accepted = 0, net_rejected = 0;
     std::vector<void*> allocs;
+};
+
+struct iss_net {
+    iss_problem* p = nullptr;
+    iss::NetImpl* impl = nullptr;
 };
 
 namespace {
@@ -460,6 +470,11 @@ int setup_level(iss_problem* p, int l) {
         eph.insert(eph.end(), eph_by_col[c].begin(), eph_by_col[c].end());
     }
     for (int c = D + 1; c < 5; ++c) off[c] = (int64_t)spec.size();
+    if (l == p->levels) {
+        L.h_vphase = vphase;
+        L.h_spec = spec;
+        L.h_eph = eph;
+    }
     int rc;
     {
         std::vector<float> m32(256), im32(256);
@@ -719,12 +734,34 @@ int precondition(iss_problem* p, int form, int prec, const double* v, double* z,
     Level& L = p->lv[l];
     if (prec == PREC_F64) {
         ISS_HIP(k_fill(PREC_F64, z, n, 0.0, s));
-        return vcycle(p, l, form, PREC_F64, z, v, s);
+        if ((rc = vcycle(p, l, form, PREC_F64, z, v, s))) return rc;
+    } else {
+        ISS_HIP(k_convert(PREC_F64, v, PREC_F32, L.w_b[PREC_F32], n, s));
+        ISS_HIP(k_fill(PREC_F32, L.w_x[PREC_F32], n, 0.0, s));
+        if ((rc = vcycle(p, l, form, PREC_F32, L.w_x[PREC_F32], L.w_b[PREC_F32], s))) return rc;
+        ISS_HIP(k_convert(PREC_F32, L.w_x[PREC_F32], PREC_F64, z, n, s));
     }
-    ISS_HIP(k_convert(PREC_F64, v, PREC_F32, L.w_b[PREC_F32], n, s));
-    ISS_HIP(k_fill(PREC_F32, L.w_x[PREC_F32], n, 0.0, s));
-    if ((rc = vcycle(p, l, form, PREC_F32, L.w_x[PREC_F32], L.w_b[PREC_F32], s))) return rc;
-    ISS_HIP(k_convert(PREC_F32, L.w_x[PREC_F32], PREC_F64, z, n, s));
+    if (p->net) {
+        // band correction of the V-cycle output from the residual it leaves,
+        // kept only if it lowers that residual (safeguard)
+        iss::NetImpl* nt = p->net->impl;
+        double* rp = net_work(nt, 0);
+        double* c = net_work(nt, 1);
+        double* rpp = net_work(nt, 2);
+        ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, PREC_F64, z, v, rp, s));
+        ISS_HIP(net_correction(nt, rp, c, n, s));
+        ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, PREC_F64, c, rp, rpp, s));
+        double a[4], b2[4];
+        if ((rc = field_norms(p, PREC_F64, rp, L.v.N, p->dim + 1, a, s))) return rc;
+        if ((rc = field_norms(p, PREC_F64, rpp, L.v.N, p->dim + 1, b2, s))) return rc;
+        const double n0 = total_norm(a, p->dim + 1), n1 = total_norm(b2, p->dim + 1);
+        if (std::isfinite(n1) && n1 < n0) {
+            ISS_HIP(k_axpby(z, 1.0, c, 1.0, n, s));
+            ++p->net_accepted;
+        } else {
+            ++p->net_rejected;
+        }
+    }
     return ISS_OK;
 }
 
@@ -750,6 +787,7 @@ int ensure_krylov(iss_problem* p, int m) {
 int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x, const double* b,
           iss_solve_info* info, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
+    p->net_accepted = p->net_rejected = 0;
     const int l = p->levels;
     Level& L = p->lv[l];
     const int D = p->dim;
@@ -871,6 +909,8 @@ int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
     ISS_HIP(hipStreamSynchronize(s));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) {
+        info->net_accepted = p->net_accepted;
+        info->net_rejected = p->net_rejected;
         info->iterations = its;
         info->relres = rel;
         info->seconds = secs;
@@ -910,6 +950,7 @@ int iss_default_options(iss_options* o) {
 
 void iss_problem_destroy(iss_problem* p) {
     if (!p) return;
+    if (p->net) p->net->p = nullptr;
     for (void* q : p->allocs) (void)hipFree(q);
     if (p->h_pinned) (void)hipHostFree(p->h_pinned);
     delete p;
@@ -1144,6 +1185,141 @@ int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double*
     ISS_HIP(hipMemcpyAsync(p->h_pinned, p->d_red, sizeof(double), hipMemcpyDeviceToHost, s));
     ISS_HIP(hipStreamSynchronize(s));
     *out = p->h_pinned[0];
+    return ISS_OK;
+}
+
+// ---- learned band correction ------------------------------------------------
+
+int iss_net_create(iss_problem* p, iss_net** out) {
+    if (!p || !out) return fail(ISS_E_INVAL, "null argument");
+    *out = nullptr;
+    if (p->dim != 3) return fail(ISS_E_INVAL, "the band correction network is 3D only");
+    const Level& L = p->lv[p->levels];
+    const int n = L.v.n;
+    const int64_t n1 = n + 1, N = L.v.N;
+    // band: Chebyshev distance <= 2 from an interface vertex
+    std::vector<uint8_t> band(N, 0);
+    for (int64_t v = 0; v < N; ++v) {
+        if (!(L.cls[v] & 1)) continue;
+        const int i = (int)(v % n1), j = (int)((v / n1) % n1), k = (int)(v / (n1 * n1));
+        for (int dk = -2; dk <= 2; ++dk)
+            for (int dj = -2; dj <= 2; ++dj)
+                for (int di = -2; di <= 2; ++di) {
+                    const int a = i + di, b = j + dj, c = k + dk;
+                    if (a < 0 || b < 0 || c < 0 || a > n || b > n || c > n) continue;
+                    band[a + n1 * (b + n1 * c)] = 1;
+                }
+    }
+    // max incident viscosity per vertex
+    std::vector<double> mumax(N, 0.0);
+    for (int64_t v = 0; v < N; ++v)
+        if (L.h_vphase[v] != SPECIAL) mumax[v] = L.mu_tab[L.h_vphase[v]];
+    constexpr int NS = KuhnTables<3>::NS;
+    for (size_t q = 0; q < L.h_spec.size(); ++q) {
+        double mx = 0;
+        for (int sl = 0; sl < NS; ++sl) {
+            const int ph = L.h_eph[q * NS + sl];
+            if (ph != OUTSIDE) mx = std::max(mx, L.mu_tab[ph]);
+        }
+        mumax[L.h_spec[q]] = mx;
+    }
+    NetSetup su;
+    su.n = n;
+    su.N = N;
+    su.nvec = 4 * N;
+    su.beta = p->opt.stab_beta;
+    for (int64_t v = 0; v < N; ++v)
+        if (band[v]) {
+            su.band.push_back((int32_t)v);
+            su.static_feat.push_back((float)(std::log10(mumax[v] > 0 ? mumax[v] : 1.0) / 4.0));
+            su.static_feat.push_back((L.cls[v] & 1) ? 1.0f : 0.0f);
+        }
+    iss_net* net = new (std::nothrow) iss_net();
+    if (!net) return fail(ISS_E_NOMEM, "host allocation failed");
+    net->p = p;
+    hipError_t e = net_create(su, &net->impl);
+    if (e != hipSuccess) {
+        delete net;
+        return fail(ISS_E_HIP, std::string("net create: ") + hipGetErrorString(e));
+    }
+    *out = net;
+    return ISS_OK;
+}
+
+void iss_net_destroy(iss_net* net) {
+    if (!net) return;
+    if (net->p && net->p->net == net) net->p->net = nullptr;
+    net_destroy(net->impl);
+    delete net;
+}
+
+int iss_net_info(const iss_net* net, int64_t* band_size, int64_t* num_params) {
+    if (!net) return fail(ISS_E_INVAL, "null net");
+    if (band_size) *band_size = net_band_size(net->impl);
+    if (num_params) *num_params = net_num_params(net->impl);
+    return ISS_OK;
+}
+
+int iss_net_band(const iss_net* net, int32_t* band) {
+    if (!net || !band) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_copy_band(net->impl, band));
+    return ISS_OK;
+}
+
+int iss_net_set_weights(iss_net* net, const float* w, iss_stream_t stream) {
+    if (!net || !w) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_set_weights(net->impl, w, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_features(iss_net* net, const double* r, double* scales, iss_stream_t stream) {
+    if (!net || !r) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_features(net->impl, r, scales, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_forward(iss_net* net, float* y, iss_stream_t stream) {
+    if (!net) return fail(ISS_E_INVAL, "null net");
+    ISS_HIP(net_forward(net->impl, y, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_targets(iss_net* net, const double* err, float* t, iss_stream_t stream) {
+    if (!net || !err || !t) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_targets(net->impl, err, t, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_backward(iss_net* net, const float* t, float* grad, double* loss, iss_stream_t stream) {
+    if (!net || !grad) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_backward(net->impl, t, grad, loss, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_correction(iss_net* net, double* c, iss_stream_t stream) {
+    if (!net || !c) return fail(ISS_E_INVAL, "null argument");
+    const Level& L = net->p->lv[net->p->levels];
+    ISS_HIP(net_output_correction(net->impl, c, (int64_t)(net->p->dim + 1) * L.v.N, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_output_grad(iss_net* net, const double* dldc, double factor, iss_stream_t stream) {
+    if (!net || !dldc) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_output_grad(net->impl, dldc, factor, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_adam_step(int64_t n, float* w, float* m, float* v, const float* g, float lr, int step,
+                  iss_stream_t stream) {
+    if (!w || !m || !v || !g || n < 0 || step < 1) return fail(ISS_E_INVAL, "bad argument");
+    ISS_HIP(net_adam(n, w, m, v, g, lr, step, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_problem_set_net(iss_problem* p, iss_net* net) {
+    if (!p) return fail(ISS_E_INVAL, "null problem");
+    if (net && net->p != p) return fail(ISS_E_INVAL, "net belongs to another problem");
+    p->net = net;
     return ISS_OK;
 }
 

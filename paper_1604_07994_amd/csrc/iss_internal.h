@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "iss_geometry.h"
 
 namespace iss {
@@ -73,5 +75,31 @@ hipError_t k_dense_matvec(const double* A, int64_t m, const double* x, double* y
                           hipStream_t s);
 hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* buoyant_flag, double rho,
                           double vol_unit, double* b, hipStream_t s);
+
+// ---- learned band correction (iss_net.hip)
+struct NetImpl;
+struct NetSetup {
+    int n;                               // finest level cells per axis (3D)
+    int64_t N, nvec;                     // vertices, (d+1) N
+    double beta;                         // stabilisation constant
+    std::vector<int32_t> band;           // band vertex ids, ascending
+    std::vector<float> static_feat;      // per band vertex: log10(max mu)/4, interface flag
+};
+hipError_t net_create(const NetSetup& s, NetImpl** out);
+void net_destroy(NetImpl* n);
+int64_t net_band_size(const NetImpl* n);
+int64_t net_num_params(const NetImpl* n);
+hipError_t net_copy_band(const NetImpl* n, int32_t* host);
+hipError_t net_set_weights(NetImpl* n, const float* w, hipStream_t s);
+hipError_t net_features(NetImpl* n, const double* r, double* scales_host, hipStream_t s);
+hipError_t net_forward(NetImpl* n, float* y_out, hipStream_t s);
+hipError_t net_targets(NetImpl* n, const double* err, float* t, hipStream_t s);
+hipError_t net_backward(NetImpl* n, const float* t, float* grad, double* loss_host, hipStream_t s);
+hipError_t net_adam(int64_t count, float* w, float* m, float* v, const float* g, float lr, int step,
+                    hipStream_t s);
+hipError_t net_correction(NetImpl* n, const double* r, double* c, int64_t nvec, hipStream_t s);
+hipError_t net_output_correction(NetImpl* n, double* c, int64_t nvec, hipStream_t s);
+hipError_t net_output_grad(NetImpl* n, const double* dldc, double factor, hipStream_t s);
+double* net_work(NetImpl* n, int which);
 
 }  // namespace iss
