@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solves: smoothing steps, applies and a plain copy (for profiler runs)")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned band-correction comparison (65^3 held-out geometries)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--quick", action="store_true", help="solves only, no apply/smoother timing")
@@ -104,6 +106,23 @@ print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h
             "sample": "oracle FGMRES + Uzawa V-cycle (same settings) on %s refined %d times (%d vertices), %d iterations "
                       "in %.1f s, scaled by vertex count to %d vertices and to the GPU's %d "
                       "iterations" % (w["name"], lv_small, r["N"], r["its"], r["seconds"], N_full, its_gpu)}
+
+
+def learned_report(seeds=(100000, 100004)):
+    """Plain vs learned-corrected FGMRES on held-out 65^3 inclusion
+    geometries with the stored trained weights (weights/band_net.npz)."""
+    import numpy as np
+    from paper_1604_07994_amd import learned
+    path = os.path.join(ROOT, "paper_1604_07994_amd", "weights", "band_net.npz")
+    w = np.load(path, allow_pickle=False)["weights"]
+    rows = learned.evaluate(w, list(seeds), levels=6, log=log)
+    return {"workload": "learned_3d 65^3, held-out seeds %s" % (list(seeds),),
+            "plain_iterations": [r["plain_iterations"] for r in rows],
+            "net_iterations": [r["net_iterations"] for r in rows],
+            "plain_seconds": [r["plain_seconds"] for r in rows],
+            "net_seconds": [r["net_seconds"] for r in rows],
+            "net_accepted": [r["net_accepted"] for r in rows],
+            "net_rejected": [r["net_rejected"] for r in rows]}
 
 
 def main():
@@ -182,6 +201,10 @@ def main():
                 "relres": info["relres"], "status": info["status"]}
         log("fp32-preconditioned %s: its %d relres %.2e %.3f s" % (forms[0], info["iterations"], info["relres"], fp32["seconds"]))
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_report()
+
     apply_gbs = {}
     smooth_ms = {}
     if not args.quick:
@@ -236,6 +259,7 @@ def main():
         "strain_over_interface": (results["strain"]["seconds"] / results["interface"]["seconds"])
         if "strain" in results and "interface" in results else None,
         "fp32_preconditioner": fp32,
+        "learned_correction": learned,
         "apply": apply_gbs,
         "smooth_step_ms": smooth_ms,
         "roofline": roof,

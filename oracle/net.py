@@ -18,7 +18,9 @@ cf. the interface discussion of Sec. 2.2).  Reading taken:
   (velocity) or s_p mu / (6 beta h^3) (pressure), mu the largest incident
   viscosity, is the correction added to the iterate on the band;
 * loss: mean squared error over band vertices and the 4 output channels,
-  against the exact error in the same units.
+  against the exact error in the same units (``mse``); the solver-side
+  training objective, the residual left after the correction, reaches this
+  module through ``backward`` with dL/dy supplied by the caller.
 
 Everything here is plain numpy in FP64, written as direct loops over the 27
 taps; the backward pass is derived by hand.

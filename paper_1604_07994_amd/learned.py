@@ -90,10 +90,10 @@ def train(seeds, levels=6, epochs=20, lr=1e-3, init_seed=0, log=print):
     log("generated %d pairs from %d geometries in %.1f s" % (len(data), len(nets), time.time() - t0))
     npar = nets[0].num_params
     rng = np.random.default_rng(init_seed)
-    # He-style initialisation scaled for 3x3x3 fan-in
-    from .binding import lib  # noqa: F401
+    # He-style initialisation for the hidden layers; the output layer starts
+    # near zero so that training starts from "no correction" (ratio 1)
     sizes = [(16, 8), (16, 16), (4, 16)]
-    init = np.concatenate([rng.normal(size=co * ci * 27) * np.sqrt(2.0 / (ci * 27)) * (0.5 if co == 4 else 1.0)
+    init = np.concatenate([rng.normal(size=co * ci * 27) * np.sqrt(2.0 / (ci * 27)) * (1e-3 if co == 4 else 1.0)
                            for co, ci in sizes]).astype(np.float32)
     wt = torch.from_numpy(init).cuda()
     m = torch.zeros_like(wt)
@@ -175,8 +175,8 @@ def main():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--train-seeds", type=int, default=24)
     ap.add_argument("--test-seeds", type=int, default=8)
-    ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--lr", type=float, default=2e-3)
     args = ap.parse_args()
     log = lambda s: print(s, flush=True)
     weights, meta = train(list(range(args.train_seeds)), args.levels, args.epochs, args.lr, log=log)
