@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--omega", type=float, default=0.6)
     ap.add_argument("--nu", type=int, default=5, help="pre- and post-smoothing steps")
+    ap.add_argument("--nu-inc", type=int, default=0,
+                    help="variable V-cycle: extra smoothing steps per level below the finest")
     ap.add_argument("--restart", type=int, default=150)
     ap.add_argument("--maxit", type=int, default=400)
     ap.add_argument("--outer", default="fgmres")
@@ -73,7 +75,7 @@ def event_time(fn, reps):
     return s.elapsed_time(e) / reps
 
 
-def cpu_baseline(w, its_gpu, omega, nu, restart):
+def cpu_baseline(w, its_gpu, omega, nu, restart, nu_inc=0):
     """The oracle (explicit CSR, same algorithm) on the host: an FGMRES solve
     of the same workload at a reduced level, timed, scaled to the full
     lattice by vertex count and to the GPU's iteration count."""
@@ -84,7 +86,7 @@ import iss_inputs
 from oracle import multigrid as mg, problem as oprob
 w = iss_inputs.workload(%r, seed=%d, levels=%d)
 H = mg.Hierarchy(w['dim'], w['macro'], w['levels'], w['coarse'], w['inclusions'], w['mu'], 'interface',
-                 omega=%r, nu1=%d, nu2=%d, coarse_mu='average', coarse_form='strain')
+                 omega=%r, nu1=%d, nu2=%d, coarse_mu='average', coarse_form='strain', nu_inc=%d)
 lv = H.levels[w['levels']]
 b = oprob.rhs_buoyancy(w['dim'], w['n'], lv.disc.elems, lv.disc.phase_e, w['buoyant']) * lv.free
 t = time.time()
@@ -94,7 +96,7 @@ print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h
 """
     lv_small = min(w["levels"], 4)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, restart, 25)
+    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, nu_inc, restart, 25)
     out = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, env=env, timeout=600)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
@@ -141,7 +143,7 @@ def main():
     forms = args.forms.split(",")
     t0 = time.time()
     P = Problem.from_workload(w, outer=args.outer, omega=args.omega, restart=args.restart,
-                              coarse_mu=args.coarse_mu, nu1=args.nu, nu2=args.nu,
+                              coarse_mu=args.coarse_mu, nu1=args.nu, nu2=args.nu, nu_inc=args.nu_inc,
                               coarse_form=None if args.coarse_form == "same" else args.coarse_form)
     log("setup %.1f s, n = %d" % (time.time() - t0, w["n"]))
     nvec = P.vector_size()
@@ -241,7 +243,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         try:
-            cpu = cpu_baseline(w, results[main_form]["iterations"], args.omega, args.nu, args.restart)
+            cpu = cpu_baseline(w, results[main_form]["iterations"], args.omega, args.nu, args.restart,
+                               args.nu_inc)
         except Exception as e:   # reported, never silently replaced
             cpu = {"error": str(e)[-300:]}
     out = {
@@ -252,8 +255,10 @@ def main():
         "config": {"workload": "%s: %d^3 vertices, %d unknowns, %d spheres mu_in %.0e, %d interface "
                                "vertices" % (w["name"], w["n"] + 1, nvec, len(w["inclusions"]),
                                              w["mu"][1], nif),
-                   "solver": "%s + Uzawa V(%d,%d), omega %.2f, restart %d, coarse viscosity %s"
-                             % (args.outer, args.nu, args.nu, args.omega, args.restart, args.coarse_mu),
+                   "solver": "%s + Uzawa V(%d,%d) +%d steps per coarser level, omega %.2f, restart %d, "
+                             "coarse viscosity %s"
+                             % (args.outer, args.nu, args.nu, args.nu_inc, args.omega, args.restart,
+                                args.coarse_mu),
                    "parallelism": "single GPU"},
         "forms": results,
         "strain_over_interface": (results["strain"]["seconds"] / results["interface"]["seconds"])

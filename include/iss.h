@@ -101,6 +101,10 @@ typedef struct {
                            * of the call; ISS_STRAIN follows the paper's swap
                            * to the strain form on coarse grids (Sec. 5),
                            * applied to every coarser level.              */
+    int nu_inc;           /* variable V-cycle (V_var, Sec. 5): level l runs
+                           * nu1 + nu_inc (L - l) pre- and nu2 + nu_inc (L - l)
+                           * post-smoothing steps, L the finest level;
+                           * 0 (default) = the same count on every level. */
 } iss_options;
 
 typedef struct {

@@ -212,12 +212,14 @@ class Hierarchy:
     """Levels n_l = m 2^l for l = coarse..fine (m macro cubes per axis)."""
 
     def __init__(self, dim, m, fine_level, coarse_level, inclusions, mu_table, form,
-                 nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None):
+                 nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None, nu_inc=0):
         """coarse_mu: 'centroid' rediscretises every level with the centroid
         rule; 'average' uses averaged_coarse_viscosity below the finest
         level.  coarse_form: viscous form of the levels below the finest
         (Sec. 5 swaps to the strain form on the coarse grid); default: the
-        same form on every level."""
+        same form on every level.  nu_inc: variable V-cycle (V_var of
+        Sec. 5), nu_inc more pre- and post-smoothing steps per level below
+        the finest."""
         self.dim = dim
         self.levels = {}
         self.P = {}
@@ -236,7 +238,7 @@ class Hierarchy:
                 self.P[l] = prolongation(dim, m * 2 ** (l - 1))
         self.fine, self.coarse = fine_level, coarse_level
         self.coarse_solver = CoarseSolver(self.levels[coarse_level])
-        self.nu1, self.nu2, self.omega = nu1, nu2, omega
+        self.nu1, self.nu2, self.omega, self.nu_inc = nu1, nu2, omega, nu_inc
 
     def prolong(self, l, xc):
         P, dim = self.P[l], self.dim
@@ -253,11 +255,12 @@ class Hierarchy:
         lv = self.levels[l]
         if l == self.coarse:
             return self.coarse_solver.solve(b)
-        x = smooth(lv, x, b, self.nu1, self.omega)
+        extra = self.nu_inc * (self.fine - l)
+        x = smooth(lv, x, b, self.nu1 + extra, self.omega)
         r = residual(lv, x, b)
         ec = self.vcycle(l - 1, np.zeros(self.levels[l - 1].K.shape[0]), self.restrict(l, r))
         x = x + self.prolong(l, ec)
-        return smooth(lv, x, b, self.nu2, self.omega)
+        return smooth(lv, x, b, self.nu2 + extra, self.omega)
 
     def solve(self, b, rtol=1e-8, maxit=100, x0=None):
         lv = self.levels[self.fine]

@@ -32,7 +32,7 @@ class Inclusion(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int),
-                ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int)]
+                ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -140,11 +140,11 @@ class Problem:
 
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
-                 coarse_form=None):
+                 coarse_form=None, nu_inc=0):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
-                      -1 if coarse_form is None else FORMS[coarse_form])
+                      -1 if coarse_form is None else FORMS[coarse_form], nu_inc)
         incs = inclusions_to_c(inclusions)
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()

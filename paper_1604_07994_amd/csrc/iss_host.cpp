@@ -152,6 +152,7 @@ struct DevBuf {
 struct Level {
     LevelView v{};
     uint8_t* d_vphase = nullptr;
+    uint8_t* d_vphase_s = nullptr;  // phase bytes in the colour-split layout
     int32_t* d_spec = nullptr;
     uint8_t* d_spec_eph = nullptr;
     std::vector<uint8_t> cls;       // per vertex: bit0 interface, bit1 boundary
@@ -169,6 +170,7 @@ struct Level {
     void* w_x[2] = {nullptr, nullptr};
     void* w_b[2] = {nullptr, nullptr};
     void* w_r[2] = {nullptr, nullptr};
+    void* w_s[2] = {nullptr, nullptr};      // split layout: xs, bs, ws (d+1 fields each)
 };
 
 struct Coarse {
@@ -485,6 +487,21 @@ int setup_level(iss_problem* p, int l) {
         if ((rc = dev_upload(p, &L.d_imu32, im32.data(), 256))) return rc;
     }
     if ((rc = dev_upload(p, &L.d_vphase, vphase.data(), vphase.size()))) return rc;
+    // colour-split layout of the smoother: rows grouped by i mod (d+1)
+    constexpr int M = D + 1;
+    const int q = (int)((n1 + M - 1) / M);
+    const int64_t Rp = (int64_t)M * q;
+    const int64_t Pp = Rp * n1;
+    const int64_t Ns = (D == 3) ? Pp * n1 : Rp * n1;
+    {
+        std::vector<uint8_t> vs((size_t)Ns, SPECIAL);
+        for (int64_t v = 0; v < N; ++v) {
+            const int64_t row = v / n1;
+            const int i = (int)(v - row * n1);
+            vs[(size_t)(row * Rp + (int64_t)(i % M) * q + i / M)] = vphase[v];
+        }
+        if ((rc = dev_upload(p, &L.d_vphase_s, vs.data(), vs.size()))) return rc;
+    }
     if ((rc = dev_upload(p, &L.d_spec, spec.data(), spec.size()))) return rc;
     if ((rc = dev_upload(p, &L.d_spec_eph, eph.data(), eph.size()))) return rc;
     LevelView& V = L.v;
@@ -505,6 +522,11 @@ int setup_level(iss_problem* p, int l) {
     V.sA = std::pow(h, D - 2);
     V.sB = std::pow(h, D - 1);
     V.sC = p->opt.stab_beta * std::pow(h, D);
+    V.q = q;
+    V.Rp = (int)Rp;
+    V.Pp = Pp;
+    V.Ns = Ns;
+    V.vphase_s = L.d_vphase_s;
     return ISS_OK;
 }
 
@@ -516,7 +538,19 @@ int ensure_work(iss_problem* p, int l, int prec) {
     if ((rc = dev_alloc(p, &L.w_x[prec], bytes))) return rc;
     if ((rc = dev_alloc(p, &L.w_b[prec], bytes))) return rc;
     if ((rc = dev_alloc(p, &L.w_r[prec], bytes))) return rc;
+    const size_t sbytes = (size_t)3 * (p->dim + 1) * L.v.Ns * (prec == PREC_F64 ? 8 : 4);
+    if ((rc = dev_alloc(p, &L.w_s[prec], sbytes))) return rc;
     return ISS_OK;
+}
+
+// split-layout buffers of a level: xs, bs, ws (d+1 fields of Ns each)
+void split_buffers(iss_problem* p, int l, int prec, void** xs, void** bs, void** ws) {
+    const Level& L = p->lv[l];
+    const size_t vec = (size_t)(p->dim + 1) * L.v.Ns * (prec == PREC_F64 ? 8 : 4);
+    char* base = (char*)L.w_s[prec];
+    *xs = base;
+    *bs = base + vec;
+    *ws = base + 2 * vec;
 }
 
 // ----------------------------------------------------------------------------
@@ -689,25 +723,37 @@ int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hip
     return ISS_OK;
 }
 
-int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, hipStream_t s) {
+// V(nu1, nu2) cycle on level l.  x_zero: x holds zero on entry (it is then
+// not read).  Smoothing runs on colour-split copies of x and b; b is packed
+// once for both smoothing phases.
+int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bool x_zero, hipStream_t s) {
     if (l == p->coarse) return coarse_solve(p, form, prec, b, x, s);
     int rc;
     if ((rc = ensure_work(p, l, prec)) || (rc = ensure_work(p, l - 1, prec))) return rc;
     Level& L = p->lv[l];
     Level& Lc = p->lv[l - 1];
-    const size_t es = prec == PREC_F64 ? 8 : 4;
-    void* work = L.w_r[prec];
-    (void)es;
-    for (int i = 0; i < p->opt.nu1; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, work, s));
+    const int nf = p->dim + 1;
+    void *xs, *bs, *ws;
+    split_buffers(p, l, prec, &xs, &bs, &ws);
+    ISS_HIP(k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s));
+    if (x_zero) ISS_HIP(k_fill(prec, xs, (int64_t)nf * L.v.Ns, 0.0, s));
+    else ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
+    const int extra = p->opt.nu_inc * (p->levels - l);      // V_var: more steps on coarser levels
+    const int nu1 = p->opt.nu1 + extra, nu2 = p->opt.nu2 + extra;
+    for (int i = 0; i < nu1; ++i)
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
+    ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
     ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
     ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
-    ISS_HIP(k_fill(prec, Lc.w_x[prec], (int64_t)(p->dim + 1) * Lc.v.N, 0.0, s));
     const int cform = (p->opt.coarse_form >= 0) ? p->opt.coarse_form : form;
-    if ((rc = vcycle(p, l - 1, cform, prec, Lc.w_x[prec], Lc.w_b[prec], s))) return rc;
+    if ((rc = vcycle(p, l - 1, cform, prec, Lc.w_x[prec], Lc.w_b[prec], true, s))) return rc;
     ISS_HIP(k_prolong_add(L.v, Lc.v, prec, Lc.w_x[prec], x, s));
-    for (int i = 0; i < p->opt.nu2; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, work, s));
+    if (nu2 > 0) {
+        ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
+        for (int i = 0; i < nu2; ++i)
+            ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
+        ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
+    }
     return ISS_OK;
 }
 
@@ -733,12 +779,10 @@ int precondition(iss_problem* p, int form, int prec, const double* v, double* z,
     if ((rc = ensure_work(p, l, prec))) return rc;
     Level& L = p->lv[l];
     if (prec == PREC_F64) {
-        ISS_HIP(k_fill(PREC_F64, z, n, 0.0, s));
-        if ((rc = vcycle(p, l, form, PREC_F64, z, v, s))) return rc;
+        if ((rc = vcycle(p, l, form, PREC_F64, z, v, true, s))) return rc;
     } else {
         ISS_HIP(k_convert(PREC_F64, v, PREC_F32, L.w_b[PREC_F32], n, s));
-        ISS_HIP(k_fill(PREC_F32, L.w_x[PREC_F32], n, 0.0, s));
-        if ((rc = vcycle(p, l, form, PREC_F32, L.w_x[PREC_F32], L.w_b[PREC_F32], s))) return rc;
+        if ((rc = vcycle(p, l, form, PREC_F32, L.w_x[PREC_F32], L.w_b[PREC_F32], true, s))) return rc;
         ISS_HIP(k_convert(PREC_F32, L.w_x[PREC_F32], PREC_F64, z, n, s));
     }
     if (p->net) {
@@ -826,77 +870,113 @@ int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
                 if (bad(rel)) { rc = ISS_E_DIVERGED; break; }
             }
         } else {
-            // right-preconditioned FGMRES(m), classical Gram-Schmidt applied twice
-            std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2);
+            // Right-preconditioned FGMRES(m) (Saad 1993) with classical
+            // Gram-Schmidt and delayed reorthogonalisation: the second
+            // projection of each new vector is fused with the first
+            // projection of the next one, so each iteration reads the basis
+            // twice (one dot pass, one update pass) instead of four times.
+            // Column j of V holds the projected, not yet reorthogonalised
+            // vector u_j (scaled to about unit length) until step j finishes
+            // it; z_j = M u_j (FGMRES accepts any z_j, and u_j differs from
+            // v_j only by a multiple plus a vector in span(v_0..v_{j-1})).
+            // Column j of the Hessenberg matrix is completed at step j + 1,
+            // so convergence is seen one V-cycle late.
+            std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
             double* V = p->d_V;
             double* Z = p->d_Z;
             double* w = p->d_w;
             double* dh = p->d_h;
+            double* hh = p->h_pinned;
+            // Givens rotations on column col (complete) and the residual estimate
+            auto close_column = [&](int col) {
+                for (int i = 0; i < col; ++i) {
+                    const double a = H[(size_t)i * m + col], c = H[(size_t)(i + 1) * m + col];
+                    H[(size_t)i * m + col] = cs[i] * a + sn[i] * c;
+                    H[(size_t)(i + 1) * m + col] = -sn[i] * a + cs[i] * c;
+                }
+                const double a = H[(size_t)col * m + col], c = H[(size_t)(col + 1) * m + col];
+                const double den = std::hypot(a, c);
+                cs[col] = den > 0 ? a / den : 1.0;
+                sn[col] = den > 0 ? c / den : 0.0;
+                H[(size_t)col * m + col] = den;
+                H[(size_t)(col + 1) * m + col] = 0.0;
+                g[col + 1] = -sn[col] * g[col];
+                g[col] = cs[col] * g[col];
+                ++its;
+                rel = std::fabs(g[col + 1]) / nb;
+                hist.push_back(rel);
+            };
             while (rel > rtol && its < maxit && rc == ISS_OK) {
-                // V_0 = r / beta
-                ISS_HIP(k_scale(V, 1.0 / beta, r, n, s));
+                ISS_HIP(k_scale(V, 1.0 / beta, r, n, s));        // u_0 = v_0 = r / beta
                 std::fill(H.begin(), H.end(), 0.0);
                 std::fill(g.begin(), g.end(), 0.0);
                 g[0] = beta;
-                int j = 0;
-                for (; j < m && its < maxit; ++j) {
+                double sig = 1.0;        // u_j = (projected vector of column j-1) / sig
+                int done = 0;            // finished Hessenberg columns in this cycle
+                bool stop = false;
+                for (int j = 0; j < m && !stop; ++j) {
                     if ((rc = precondition(p, form, prec, V + (size_t)j * n, Z + (size_t)j * n, s))) return rc;
                     ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_APPLY, PREC_F64, Z + (size_t)j * n, nullptr, w, s));
-                    // classical Gram-Schmidt h = V^T w, w -= V h; a second pass
-                    // only when the norm drops below 1/sqrt(2) of its value
-                    // before projection (Daniel-Gragg-Kaufman-Stewart test)
-                    double* hh = p->h_pinned;
-                    ISS_HIP(k_multidot(V, n, j + 1, w, n, p->d_partial, dh, s, 1));
-                    ISS_HIP(k_multiaxpy(w, V, n, j + 1, dh, -1.0, n, s));
-                    ISS_HIP(k_field_sumsq(PREC_F64, w, n, 1, p->d_partial, dh + (2 * m + 3), s));
-                    ISS_HIP(hipMemcpyAsync(hh, dh, (2 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+                    // pass 1: c = V_{<j}^T u_j, d = V_{<j}^T w, u.u, u.w, w.w
+                    ISS_HIP(k_dots2(V, n, j, V + (size_t)j * n, w, n, p->d_partial, dh, s));
+                    ISS_HIP(hipMemcpyAsync(hh, dh, (2 * j + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
                     ISS_HIP(hipStreamSynchronize(s));
-                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
-                    const double before = std::sqrt(std::max(hh[j + 1], 0.0));
-                    double hn = std::sqrt(std::max(hh[2 * m + 3], 0.0));
-                    if (hn < 0.7071067811865476 * before) {
-                        double* hp = dh + (m + 2);
-                        ISS_HIP(k_multidot(V, n, j + 1, w, n, p->d_partial, hp, s, 0));
-                        ISS_HIP(k_multiaxpy(w, V, n, j + 1, hp, -1.0, n, s));
-                        ISS_HIP(k_field_sumsq(PREC_F64, w, n, 1, p->d_partial, dh + (2 * m + 3), s));
-                        ISS_HIP(hipMemcpyAsync(hh, dh, (2 * m + 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+                    const double* c = hh;
+                    const double* d = hh + j;
+                    const double uu = hh[2 * j], uw = hh[2 * j + 1], ww = hh[2 * j + 2];
+                    double cc = 0, cd = 0, dd = 0;
+                    for (int i = 0; i < j; ++i) { cc += c[i] * c[i]; cd += c[i] * d[i]; dd += d[i] * d[i]; }
+                    const double a2 = uu - cc;
+                    if (!std::isfinite(a2) || !std::isfinite(ww)) { rc = ISS_E_DIVERGED; break; }
+                    if (j > 0) {
+                        // finish column j - 1: A z_{j-1} = ... + sig (V_{<j} c + alpha v_j)
+                        const double alpha = a2 > 1e-28 * uu ? std::sqrt(a2) : 0.0;
+                        for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += sig * c[i];
+                        H[(size_t)j * m + (j - 1)] = sig * alpha;
+                        close_column(j - 1);
+                        done = j;
+                        if (!std::isfinite(rel)) { rc = ISS_E_DIVERGED; break; }
+                        if (rel <= rtol || alpha == 0.0 || its >= maxit) break;   // z_j is not used
+                    }
+                    const double alpha = std::sqrt(std::max(a2, 0.0));
+                    const double e = (uw - cd) / alpha;
+                    for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = d[i];
+                    H[(size_t)j * m + j] = e;
+                    // length of the new projected vector (Pythagoras; only a scale)
+                    const double r2 = ww - dd - e * e;
+                    double snew = r2 > 1e-24 * ww ? std::sqrt(r2) : 1e-12 * std::sqrt(ww);
+                    if (!(snew > 0) || !std::isfinite(snew)) snew = 1.0;
+                    // pass 2: v_j = (u_j - V c) / alpha; u_{j+1} = (w - V d - e v_j) / snew
+                    ISS_HIP(k_dcgs_update(V, n, j, dh, dh + j, w, 1.0 / alpha, e, 1.0 / snew, n, s));
+                    sig = snew;
+                    if (j == m - 1) {
+                        // restart: finish the last column with one more dot pass
+                        ISS_HIP(k_dots2(V, n, m, V + (size_t)m * n, V + (size_t)m * n, n, p->d_partial, dh, s));
+                        ISS_HIP(hipMemcpyAsync(hh, dh, (2 * m + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
                         ISS_HIP(hipStreamSynchronize(s));
-                        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hh[m + 2 + i];
-                        hn = std::sqrt(std::max(hh[2 * m + 3], 0.0));
-                        ++p->reorth_count;
+                        double c2 = 0;
+                        for (int i = 0; i < m; ++i) c2 += hh[i] * hh[i];
+                        const double b2 = hh[2 * m] - c2;
+                        for (int i = 0; i < m; ++i) H[(size_t)i * m + (m - 1)] += sig * hh[i];
+                        H[(size_t)m * m + (m - 1)] = sig * (b2 > 1e-28 * hh[2 * m] ? std::sqrt(b2) : 0.0);
+                        close_column(m - 1);
+                        done = m;
+                        if (!std::isfinite(rel)) { rc = ISS_E_DIVERGED; break; }
                     }
-                    H[(size_t)(j + 1) * m + j] = hn;
-                    if (hn > 0) ISS_HIP(k_scale(V + (size_t)(j + 1) * n, 1.0 / hn, w, n, s));
-                    for (int i = 0; i < j; ++i) {
-                        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-                    }
-                    const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-                    const double den = std::hypot(a, c);
-                    cs[j] = a / den;
-                    sn[j] = c / den;
-                    H[(size_t)j * m + j] = den;
-                    H[(size_t)(j + 1) * m + j] = 0.0;
-                    g[j + 1] = -sn[j] * g[j];
-                    g[j] = cs[j] * g[j];
-                    ++its;
-                    rel = std::fabs(g[j + 1]) / nb;
-                    hist.push_back(rel);
-                    if (!std::isfinite(rel)) { rc = ISS_E_DIVERGED; break; }
-                    if (rel <= rtol || hn == 0.0) { ++j; break; }
                 }
                 if (rc != ISS_OK) break;
+                const int jn = done;
+                if (jn == 0) break;
                 // y = H^{-1} g ; x += Z y
-                std::vector<double> y(j);
-                for (int i = j - 1; i >= 0; --i) {
+                std::vector<double> y(jn);
+                for (int i = jn - 1; i >= 0; --i) {
                     double t = g[i];
-                    for (int k = i + 1; k < j; ++k) t -= H[(size_t)i * m + k] * y[k];
+                    for (int k = i + 1; k < jn; ++k) t -= H[(size_t)i * m + k] * y[k];
                     y[i] = t / H[(size_t)i * m + i];
                 }
                 std::copy(y.begin(), y.end(), p->h_pinned);
-                ISS_HIP(hipMemcpyAsync(dh, p->h_pinned, j * sizeof(double), hipMemcpyHostToDevice, s));
-                ISS_HIP(k_multiaxpy(x, Z, n, j, dh, 1.0, n, s));
+                ISS_HIP(hipMemcpyAsync(dh, p->h_pinned, jn * sizeof(double), hipMemcpyHostToDevice, s));
+                ISS_HIP(k_multiaxpy(x, Z, n, jn, dh, 1.0, n, s));
                 ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, PREC_F64, x, b, r, s));
                 if ((rc = field_norms(p, PREC_F64, r, N, D + 1, sq, s))) return rc;
                 beta = total_norm(sq, D + 1);
@@ -945,6 +1025,7 @@ int iss_default_options(iss_options* o) {
     o->restart = 40;
     o->coarse_mu = ISS_COARSE_MU_AVERAGE;
     o->coarse_form = -1;
+    o->nu_inc = 0;
     return ISS_OK;
 }
 
@@ -989,7 +1070,7 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     p->mu.resize(256, 1.0);
     if (opt) p->opt = *opt;
     else iss_default_options(&p->opt);
-    if (p->opt.nu1 < 0 || p->opt.nu2 < 0 || !(p->opt.stab_beta > 0) || p->opt.restart < 1 ||
+    if (p->opt.nu1 < 0 || p->opt.nu2 < 0 || p->opt.nu_inc < 0 || !(p->opt.stab_beta > 0) || p->opt.restart < 1 ||
         (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES) ||
         (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
         p->opt.coarse_form < -1 || p->opt.coarse_form > 2) {
@@ -1129,11 +1210,15 @@ int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps, void* 
     if ((rc = check_form(form)) || (rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
     if ((rc = ensure_work(p, level, prec))) return rc;
     Level& L = p->lv[level];
-    const size_t es = prec == PREC_F64 ? 8 : 4;
-    void* work = L.w_r[prec];
-    (void)es;
+    const hipStream_t s = (hipStream_t)stream;
+    const int nf = p->dim + 1;
+    void *xs, *bs, *ws;
+    split_buffers(p, level, prec, &xs, &bs, &ws);
+    ISS_HIP(k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s));
+    ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
     for (int i = 0; i < nsteps; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, x, b, work, (hipStream_t)stream));
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
+    ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
     return ISS_OK;
 }
 
@@ -1166,7 +1251,7 @@ int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b, iss_s
     if (!p || !x || !b) return fail(ISS_E_INVAL, "null argument");
     int rc;
     if ((rc = check_form(form)) || (rc = check_prec(prec))) return rc;
-    return vcycle(p, p->levels, form, prec, x, b, (hipStream_t)stream);
+    return vcycle(p, p->levels, form, prec, x, b, false, (hipStream_t)stream);
 }
 
 int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x, const double* b,

@@ -34,7 +34,14 @@ struct LevelView {
     const float* mu32;
     const float* imu32;
     double sA, sB, sC;       // h^(d-2), h^(d-1), beta h^d
+    // colour-split layout used inside smoothing calls: vertex (i, j, k) at
+    // k Pp + j Rp + (i mod (d+1)) q + i div (d+1); Ns entries per field
+    int q, Rp;
+    int64_t Pp, Ns;
+    const uint8_t* vphase_s; // phase bytes in the split layout (padding SPECIAL)
 };
+
+enum { SPLIT_PACK = 0, SPLIT_UNPACK = 1 };
 
 // Kernel launchers (iss_kernels.hip).  `prec` selects double / float
 // vectors.  Each returns hipSuccess or the launch error.
@@ -42,9 +49,14 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
                          size_t bytes32);
 hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec,
                    const void* x, const void* b, void* y, hipStream_t s);
-// one Uzawa step; work holds d+1 fields of scratch (the level's r vector)
-hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* x,
-                         const void* b, void* work, hipStream_t s);
+// one Uzawa step on split-layout vectors xs, bs (d+1 fields of Ns each);
+// ws holds d+1 split fields of scratch
+hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs,
+                         const void* bs, void* ws, hipStream_t s);
+// canonical <-> split copy of nf fields (dir SPLIT_PACK: canonical in, split
+// out with zero padding; SPLIT_UNPACK: split in, canonical out)
+hipError_t k_split(const LevelView& L, int prec, int nf, const void* in, void* out, int dir,
+                   hipStream_t s);
 hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf,
                       void* rc, hipStream_t s);
 hipError_t k_prolong_add(const LevelView& Lf, const LevelView& Lc, int prec, const void* ec,
@@ -60,6 +72,13 @@ hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* par
 // if with_self; partial holds 65536 doubles.
 hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
                       double* partial, double* out, hipStream_t s, int with_self = 0);
+// Delayed classical Gram-Schmidt: out[0..k) = V^T a, out[k..2k) = V^T b,
+// out[2k] = a.a, out[2k+1] = a.b, out[2k+2] = b.b (partial: 65536 doubles)
+hipError_t k_dots2(const double* V, int64_t ldv, int k, const double* a, const double* b, int64_t n,
+                   double* partial, double* out, hipStream_t s);
+// V_k = (V_k - sum_i c_i V_i) inv_alpha;  V_{k+1} = (w - sum_i d_i V_i - e V_k) inv_s
+hipError_t k_dcgs_update(double* V, int64_t ldv, int k, const double* c, const double* d, const double* w,
+                         double inv_alpha, double ecoef, double inv_s, int64_t n, hipStream_t s);
 // y += alpha * sum_i c[i] X_i  (c on device)
 hipError_t k_multiaxpy(double* y, const double* X, int64_t ldx, int k, const double* c,
                        double alpha, int64_t n, hipStream_t s);

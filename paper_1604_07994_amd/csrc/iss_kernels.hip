@@ -43,6 +43,25 @@ template <> struct Prec<float> {
     __device__ static float imu(const LevelView& L, int ph) { return L.imu32[ph]; }
 };
 
+// Table lookup by phase: a wave whose lanes share one phase (the common case
+// inside a subdomain) reads the entry once through the scalar cache.
+template <typename C>
+__device__ __forceinline__ C phase_lookup(const C* __restrict__ tab, int ph) {
+    const int p0 = __builtin_amdgcn_readfirstlane(ph);
+    if (__all(ph == p0)) return tab[p0];
+    return tab[ph];
+}
+
+template <typename C> struct PrecU;
+template <> struct PrecU<double> {
+    __device__ static double mu(const LevelView& L, int ph) { return phase_lookup(L.mu64, ph); }
+    __device__ static double imu(const LevelView& L, int ph) { return phase_lookup(L.imu64, ph); }
+};
+template <> struct PrecU<float> {
+    __device__ static float mu(const LevelView& L, int ph) { return phase_lookup(L.mu32, ph); }
+    __device__ static float imu(const LevelView& L, int ph) { return phase_lookup(L.imu32, ph); }
+};
+
 // ----------------------------------------------------------------------------
 // thread -> vertex maps
 
@@ -366,10 +385,179 @@ __global__ __launch_bounds__(256) void k_apply_special(LevelView L, const T* __r
 }
 
 // ----------------------------------------------------------------------------
-// Uzawa smoother pieces
+// Uzawa smoother in the colour-split layout
+//
+// During a smoothing call every field lives in a second layout: row by row,
+// the vertices of a row grouped by i mod M (M = d + 1 colours),
+//     (i, j, k) -> k Pp + j Rp + (i mod M) q + i div M,
+// q = ceil((n + 1) / M), Rp = M q, Pp = (n + 1) Rp.  The vertices of colour
+// c = (i + j + k) mod M in a row form the single run i mod M = (c - j - k)
+// mod M, so a colour phase reads and writes unit-stride runs instead of
+// every M-th element.  Row padding (i > n) is written as zero by the pack
+// kernel and never touched by the smoother.
 
-// velocity: one colour phase of the symmetric Gauss-Seidel sweep on
-// A u = f - B^T p.  BWD selects the reversed component order.
+template <int D>
+__device__ __forceinline__ int64_t sidx(const LevelView& L, int i, int j, int k) {
+    constexpr int M = D + 1;
+    return (int64_t)k * L.Pp + (int64_t)j * L.Rp + (int64_t)(i % M) * L.q + i / M;
+}
+
+// split-layout offsets of the i-1 and i+1 neighbours of a vertex in run s
+struct XOff {
+    int64_t m, p;
+};
+
+template <int D>
+__device__ __forceinline__ XOff x_offsets(const LevelView& L, int s) {
+    constexpr int M = D + 1;
+    XOff o;
+    o.m = (s > 0) ? -(int64_t)L.q : (int64_t)(M - 1) * L.q - 1;
+    o.p = (s < M - 1) ? (int64_t)L.q : 1 - (int64_t)(M - 1) * L.q;
+    return o;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t snb(const LevelView& L, const XOff& xo, int o) {
+    constexpr auto& T = Kuhn<D>::T;
+    const int dx = T.off[o][0];
+    return (dx < 0 ? xo.m : (dx > 0 ? xo.p : (int64_t)0)) + (int64_t)T.off[o][1] * L.Rp +
+           (int64_t)T.off[o][2] * L.Pp;
+}
+
+__device__ __forceinline__ int64_t split_thread() {
+    return xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+}
+
+// thread g of a colour phase -> interior vertex of that colour (run s)
+template <int D>
+__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int64_t g, int& s,
+                                                    int64_t& v) {
+    constexpr int M = D + 1;
+    const int m = L.n - 1;
+    const int tr = m / M + 1;                    // run positions covering i = 1..m
+    const int t = (int)(g % tr);
+    const int64_t row = g / tr;
+    int j, k;
+    if (D == 3) {
+        j = 1 + (int)(row % m);
+        k = 1 + (int)(row / m);
+        if (k > m) return false;
+    } else {
+        j = 1 + (int)row;
+        k = 0;
+        if (j > m) return false;
+    }
+    s = (colour - j - k) % M;
+    if (s < 0) s += M;
+    const int i = M * t + s;
+    if (i < 1 || i > m) return false;
+    v = (int64_t)k * L.Pp + (int64_t)j * L.Rp + (int64_t)s * L.q + t;
+    return true;
+}
+
+// thread g of an all-interior pass -> interior vertex (run s)
+template <int D>
+__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t g, int& s, int64_t& v) {
+    constexpr int M = D + 1;
+    const int m = L.n - 1;
+    const int r = (int)(g % L.Rp);
+    const int64_t row = g / L.Rp;
+    int j, k;
+    if (D == 3) {
+        j = 1 + (int)(row % m);
+        k = 1 + (int)(row / m);
+        if (k > m) return false;
+    } else {
+        j = 1 + (int)row;
+        k = 0;
+        if (j > m) return false;
+    }
+    s = r / L.q;
+    const int i = M * (r - s * L.q) + s;
+    if (i < 1 || i > m) return false;
+    v = (int64_t)k * L.Pp + (int64_t)j * L.Rp + r;
+    return true;
+}
+
+template <int D>
+inline int64_t split_colour_threads(int n) {
+    const int m = n - 1;
+    if (m <= 0) return 0;
+    return (int64_t)(m / (D + 1) + 1) * m * (D == 3 ? m : 1);
+}
+
+template <int D>
+inline int64_t split_all_threads(const LevelView& L) {
+    const int m = L.n - 1;
+    if (m <= 0) return 0;
+    return (int64_t)L.Rp * m * (D == 3 ? m : 1);
+}
+
+template <int D, int NF, typename T, typename C>
+__device__ __forceinline__ void load_split(const LevelView& L, const T* __restrict__ xs, int64_t v,
+                                           const XOff& xo, int f0, C (&V)[NF][KuhnTables<D>::NB]) {
+    constexpr int NB = KuhnTables<D>::NB;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int o = 0; o < NB; ++o) V[f][o] = (C)xs[(int64_t)(f0 + f) * L.Ns + v + snb<D>(L, xo, o)];
+}
+
+// guarded split-layout loads around a special vertex (may be on the boundary)
+template <int D, int NF, typename T, typename C>
+__device__ __forceinline__ void load_guarded_split(const LevelView& L, const T* __restrict__ xs,
+                                                   const int (&ijk)[3], int f0,
+                                                   C (&V)[NF][KuhnTables<D>::NB]) {
+    constexpr auto& TT = Kuhn<D>::T;
+    constexpr int NB = KuhnTables<D>::NB;
+#pragma unroll
+    for (int o = 0; o < NB; ++o) {
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int c = ijk[a] + TT.off[o][a];
+            in = in && (c >= 0) && (c <= L.n);
+        }
+        const int64_t e = in ? sidx<D>(L, ijk[0] + TT.off[o][0], ijk[1] + TT.off[o][1], ijk[2] + TT.off[o][2])
+                             : (int64_t)0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) V[f][o] = in ? (C)xs[(int64_t)(f0 + f) * L.Ns + e] : (C)0;
+    }
+}
+
+// canonical (x fastest) <-> colour-split copies of nf fields.  The pack
+// walks the split positions (padding included, written as zero); the
+// unpack walks the canonical positions.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_pack_t(LevelView L, const T* __restrict__ in, T* __restrict__ out) {
+    constexpr int M = D + 1;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t per = L.Ns;
+    if (e >= per) return;
+    const int f = blockIdx.y;
+    const int64_t row = e / L.Rp;
+    const int r = (int)(e - row * L.Rp);
+    const int s = r / L.q;
+    const int i = M * (r - s * L.q) + s;
+    const int64_t n1 = L.n + 1;
+    out[(int64_t)f * per + e] = (i <= L.n) ? in[(int64_t)f * L.N + row * n1 + i] : (T)0;
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_unpack_t(LevelView L, const T* __restrict__ in, T* __restrict__ out) {
+    constexpr int M = D + 1;
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= L.N) return;
+    const int f = blockIdx.y;
+    const int64_t n1 = L.n + 1;
+    const int64_t row = v / n1;
+    const int i = (int)(v - row * n1);
+    out[(int64_t)f * L.N + v] = in[(int64_t)f * L.Ns + row * L.Rp + (int64_t)(i % M) * L.q + i / M];
+}
+
+// Velocity: one colour phase of the symmetric Gauss-Seidel sweep on
+// A u = f - B^T p (eq. Uzawa_smooth).  BWD selects the reversed component
+// order of the block update.
 template <int D, int F, bool BWD, typename C>
 __device__ __forceinline__ void block_gs_update(C (&r)[D], const C (&Dm)[D][D], C (&du)[D]) {
     if (!BWD) {
@@ -394,41 +582,51 @@ __device__ __forceinline__ void block_gs_update(C (&r)[D], const C (&Dm)[D][D], 
 // g = f - B^T p on interior isoviscous vertices (p is fixed during the
 // velocity sweep, so the coupling term is formed once per sweep).
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_vel_rhs_bulk(LevelView L, const T* __restrict__ x,
-                                                      const T* __restrict__ b, T* __restrict__ g) {
+__global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restrict__ xs,
+                                                   const T* __restrict__ bs, T* __restrict__ g) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    int i, j, k;
-    if (!interior_vertex<D>(L, 0, 1, blockIdx.x, i, j, k)) return;
-    const int64_t v = i + j * L.sy + k * L.sz;
-    if (L.vphase[v] == SPECIAL) return;
+    int s;
+    int64_t v;
+    if (!split_all_vertex<D>(L, split_thread(), s, v)) return;
+    const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
-    C P[1][NB];
-    load_interior<D, 1, T, C>(L, x, v, D, P);
+    const int ph = L.vphase_s[v];
+    C P[1][NB], bl[D];
+    load_split<D, 1, T, C>(L, xs, v, xo, D, P);
+#pragma unroll
+    for (int l = 0; l < D; ++l) bl[l] = (C)bs[(int64_t)l * L.Ns + v];
+    if (ph == SPECIAL) return;
 #pragma unroll
     for (int l = 0; l < D; ++l) {
         C acc = 0;
 #pragma unroll
         for (int o = 1; o < NB; ++o) acc += E.Sbt[l][o] * P[0][o];
-        g[(int64_t)l * L.N + v] = (T)((C)b[(int64_t)l * L.N + v] - (C)L.sB * acc);
+        g[(int64_t)l * L.Ns + v] = (T)(bl[l] - (C)L.sB * acc);
     }
 }
 
 template <int D, int F, bool BWD, typename T>
-__device__ __forceinline__ void gs_vel_bulk_body(const LevelView& L, int64_t bid, int colour, T* __restrict__ x,
-                                                 const T* __restrict__ g) {
+__global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
+                                                  const T* __restrict__ g) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    int i, j, k;
-    if (!interior_vertex<D>(L, colour, D + 1, bid, i, j, k)) return;
-    const int64_t v = i + j * L.sy + k * L.sz;
-    const int ph = L.vphase[v];
-    if (ph == SPECIAL) return;
+    int s;
+    int64_t v;
+    if (!split_colour_vertex<D>(L, colour, split_thread(), s, v)) return;
+    const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
-    const C smu = Prec<C>::mu(L, ph) * (C)L.sA;
+    // every load is issued before the phase test (all addresses are
+    // interior, so the loads are in bounds for special vertices too)
+    const int ph = L.vphase_s[v];
+    C gl[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) gl[l] = (C)g[(int64_t)l * L.Ns + v];
     if (F == FORM_STRAIN) {
         C U[D][NB];
-        load_interior<D, D, T, C>(L, x, v, 0, U);
+        load_split<D, D, T, C>(L, xs, v, xo, 0, U);
+        if (ph == SPECIAL) return;
+        const C smu = PrecU<C>::mu(L, ph) * (C)L.sA;
         C r[D], Dm[D][D], du[D];
 #pragma unroll
         for (int l = 0; l < D; ++l) {
@@ -439,86 +637,79 @@ __device__ __forceinline__ void gs_vel_bulk_body(const LevelView& L, int64_t bid
                 for (int o = 0; o < NB; ++o) acc += E.Svis[1][l][kk][o] * U[kk][o];
                 Dm[l][kk] = smu * E.Svis[1][l][kk][0];
             }
-            r[l] = (C)g[(int64_t)l * L.N + v] - smu * acc;
+            r[l] = gl[l] - smu * acc;
         }
         block_gs_update<D, F, BWD, C>(r, Dm, du);
 #pragma unroll
-        for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)(U[l][0] + du[l]);
+        for (int l = 0; l < D; ++l) xs[(int64_t)l * L.Ns + v] = (T)(U[l][0] + du[l]);
     } else {
-        // decoupled components: u_l = (g_l / (mu sA) - sum_nb w u_l) / w_0
+        // decoupled components: u_l = (g_l - mu sA sum_nb w u_l) / (mu sA w_0);
+        // the neighbours are the runs of colours c - 1 and c + 1 only
+        C nb[D][2 * D];
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+            for (int o = 1; o <= 2 * D; ++o) nb[l][o - 1] = (C)xs[(int64_t)l * L.Ns + v + snb<D>(L, xo, o)];
+        if (ph == SPECIAL) return;
+        const C smu = PrecU<C>::mu(L, ph) * (C)L.sA;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-            T* ul = x + (int64_t)l * L.N + v;
             C acc = 0;
 #pragma unroll
-            for (int o = 1; o <= 2 * D; ++o) acc += E.Svis[0][l][l][o] * (C)ul[nb_lin<D>(L, o)];
+            for (int o = 1; o <= 2 * D; ++o) acc += E.Svis[0][l][l][o] * nb[l][o - 1];
             const C w0 = smu * E.Svis[0][l][l][0];
-            ul[0] = (T)(((C)g[(int64_t)l * L.N + v] - smu * acc) / w0);
+            xs[(int64_t)l * L.Ns + v] = (T)((gl[l] - smu * acc) / w0);
         }
     }
 }
 
 template <int D, int F, bool BWD, typename T>
-__device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int64_t s, int colour,
-                                                    T* __restrict__ x, const T* __restrict__ b) {
+__global__ __launch_bounds__(256) void k_gs_vel_special_s(LevelView L, int colour, T* __restrict__ xs,
+                                                          const T* __restrict__ bs) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    if (s >= L.spec_off[colour + 1]) return;
-    const int64_t v = L.spec[s];
+    const int64_t sp = L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
-    vertex_ijk<D>(L, v, ijk);
+    vertex_ijk<D>(L, L.spec[sp], ijk);
     if (on_boundary<D>(L, ijk)) return;          // Dirichlet velocity
+    const int64_t v = sidx<D>(L, ijk[0], ijk[1], ijk[2]);
     C U[D][NB], P[1][NB];
-    load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
-    load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
+    load_guarded_split<D, D, T, C>(L, xs, ijk, 0, U);
+    load_guarded_split<D, 1, T, C>(L, xs, ijk, D, P);
     RowAcc<D, F, true, false, C> r;
-    element_rows<D, F, true, false, true, false, C>(L, s, U, P[0], P[0], r);
+    element_rows<D, F, true, false, true, false, C>(L, sp, U, P[0], P[0], r);
     C res[D], Dm[D][D], du[D];
 #pragma unroll
     for (int l = 0; l < D; ++l) {
-        res[l] = (C)b[(int64_t)l * L.N + v] - (C)L.sB * r.abt[l] - (C)L.sA * r.au[l];
+        res[l] = (C)bs[(int64_t)l * L.Ns + v] - (C)L.sB * r.abt[l] - (C)L.sA * r.au[l];
 #pragma unroll
         for (int k = 0; k < D; ++k) Dm[l][k] = (C)L.sA * r.Dm[l][k];
     }
     block_gs_update<D, F, BWD, C>(res, Dm, du);
 #pragma unroll
-    for (int l = 0; l < D; ++l) x[(int64_t)l * L.N + v] = (T)((C)x[(int64_t)l * L.N + v] + du[l]);
+    for (int l = 0; l < D; ++l) xs[(int64_t)l * L.Ns + v] = (T)(U[l][0] + du[l]);
 }
 
-// pressure: one colour phase of the forward Gauss-Seidel sweep on
-// C delta = B u - C p - g started from delta = 0.
-// One colour phase of the symmetric velocity sweep: the bulk launch reads
-// g = f - B^T p, the special launch forms its rows from the incident
-// elements.
-template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_bulk(LevelView L, int colour, T* __restrict__ x,
-                                                     const T* __restrict__ g) {
-    gs_vel_bulk_body<D, F, BWD, T>(L, blockIdx.x, colour, x, g);
-}
-
-template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_special(LevelView L, int colour, T* __restrict__ x,
-                                                        const T* __restrict__ b) {
-    gs_vel_special_body<D, F, BWD, T>(L, L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x,
-                                      colour, x, b);
-}
-
-// s = B u - C p - g on interior isoviscous vertices (u and p are fixed
-// during the pressure sweep).
+// Pressure: s = B u - C p - g on interior isoviscous vertices (u and p are
+// fixed during the pressure sweep), then one forward colour sweep of
+// Gauss-Seidel on C delta = s from delta = 0.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_p_rhs_bulk(LevelView L, const T* __restrict__ x,
-                                                    const T* __restrict__ b, T* __restrict__ sres) {
+__global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
+                                                 const T* __restrict__ bs, T* __restrict__ sres) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    int i, j, k;
-    if (!interior_vertex<D>(L, 0, 1, blockIdx.x, i, j, k)) return;
-    const int64_t v = i + j * L.sy + k * L.sz;
-    const int ph = L.vphase[v];
-    if (ph == SPECIAL) return;
+    int s;
+    int64_t v;
+    if (!split_all_vertex<D>(L, split_thread(), s, v)) return;
+    const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
+    const int ph = L.vphase_s[v];
     C U[D][NB], P[1][NB];
-    load_interior<D, D, T, C>(L, x, v, 0, U);
-    load_interior<D, 1, T, C>(L, x, v, D, P);
+    load_split<D, D, T, C>(L, xs, v, xo, 0, U);
+    load_split<D, 1, T, C>(L, xs, v, xo, D, P);
+    const C bp = (C)bs[(int64_t)D * L.Ns + v];
+    if (ph == SPECIAL) return;
     C dv = 0;
 #pragma unroll
     for (int kk = 0; kk < D; ++kk)
@@ -527,59 +718,50 @@ __global__ __launch_bounds__(256) void k_p_rhs_bulk(LevelView L, const T* __rest
     C cp = E.Sc[0] * P[0][0];
 #pragma unroll
     for (int o = 1; o <= 2 * D; ++o) cp += E.Sc[o] * P[0][o];
-    const C sci = (C)L.sC * Prec<C>::imu(L, ph);
-    sres[v] = (T)((C)L.sB * dv - sci * cp - (C)b[(int64_t)D * L.N + v]);
+    const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
+    sres[v] = (T)((C)L.sB * dv - sci * cp - bp);
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void gs_p_bulk_body(const LevelView& L, int64_t bid, int colour,
-                                               const T* __restrict__ sres, T* __restrict__ delta) {
+__global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T* __restrict__ sres,
+                                                T* __restrict__ delta) {
     using C = T;
-    int i, j, k;
-    if (!interior_vertex<D>(L, colour, D + 1, bid, i, j, k)) return;
-    const int64_t v = i + j * L.sy + k * L.sz;
-    const int ph = L.vphase[v];
-    if (ph == SPECIAL) return;
+    int s;
+    int64_t v;
+    if (!split_colour_vertex<D>(L, colour, split_thread(), s, v)) return;
+    const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
+    const int ph = L.vphase_s[v];
+    C nb[2 * D];
+#pragma unroll
+    for (int o = 1; o <= 2 * D; ++o) nb[o - 1] = (C)delta[v + snb<D>(L, xo, o)];
+    const C sv = (C)sres[v];
+    if (ph == SPECIAL) return;
     C cd = 0;
 #pragma unroll
-    for (int o = 1; o <= 2 * D; ++o) cd += E.Sc[o] * (C)delta[v + nb_lin<D>(L, o)];
-    const C sci = (C)L.sC * Prec<C>::imu(L, ph);
-    delta[v] = (T)(((C)sres[v] - sci * cd) / (sci * E.Sc[0]));
+    for (int o = 1; o <= 2 * D; ++o) cd += E.Sc[o] * nb[o - 1];
+    const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
+    delta[v] = (T)((sv - sci * cd) / (sci * E.Sc[0]));
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void gs_p_special_body(const LevelView& L, int64_t s, int colour,
-                                                  const T* __restrict__ x, const T* __restrict__ b,
-                                                  T* __restrict__ delta) {
+__global__ __launch_bounds__(256) void k_gs_p_special_s(LevelView L, int colour, const T* __restrict__ xs,
+                                                        const T* __restrict__ bs, T* __restrict__ delta) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    if (s >= L.spec_off[colour + 1]) return;
-    const int64_t v = L.spec[s];
+    const int64_t sp = L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
-    vertex_ijk<D>(L, v, ijk);
+    vertex_ijk<D>(L, L.spec[sp], ijk);
+    const int64_t v = sidx<D>(L, ijk[0], ijk[1], ijk[2]);
     C U[D][NB], P[1][NB], Dl[1][NB];
-    load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
-    load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
-    load_guarded<D, 1, T, C>(L, delta, v, ijk, 0, Dl);
+    load_guarded_split<D, D, T, C>(L, xs, ijk, 0, U);
+    load_guarded_split<D, 1, T, C>(L, xs, ijk, D, P);
+    load_guarded_split<D, 1, T, C>(L, delta, ijk, 0, Dl);
     RowAcc<D, FORM_GRADIENT, false, true, C> r;
-    element_rows<D, FORM_GRADIENT, false, true, true, true, C>(L, s, U, P[0], Dl[0], r);
-    const C sres = (C)L.sB * r.bdiv - (C)L.sC * r.cp - (C)b[(int64_t)D * L.N + v];
+    element_rows<D, FORM_GRADIENT, false, true, true, true, C>(L, sp, U, P[0], Dl[0], r);
+    const C sres = (C)L.sB * r.bdiv - (C)L.sC * r.cp - (C)bs[(int64_t)D * L.Ns + v];
     delta[v] = (T)((sres - (C)L.sC * r.cd) / ((C)L.sC * r.cjj));
-}
-
-// One colour phase of the pressure sweep (bulk and special launches).
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_bulk(LevelView L, int colour, const T* __restrict__ sres,
-                                                   T* __restrict__ delta) {
-    gs_p_bulk_body<D, T>(L, blockIdx.x, colour, sres, delta);
-}
-
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_special(LevelView L, int colour, const T* __restrict__ x,
-                                                      const T* __restrict__ b, T* __restrict__ delta) {
-    gs_p_special_body<D, T>(L, L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x, colour, x, b,
-                            delta);
 }
 
 template <typename T>
@@ -743,6 +925,84 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restri
     }
 }
 
+// Gram-Schmidt with delayed reorthogonalisation: one pass computes, for a
+// tile of basis vectors V_i, the dot products V_i.a and V_i.b; tile 0 also
+// accumulates a.a, a.b and b.b.  Partial sums per block; slots [0, k) hold
+// V.a, [k, 2k) V.b, then a.a, a.b, b.b.
+__global__ __launch_bounds__(256) void k_dots2_partial(const double* __restrict__ V, int64_t ldv, int k,
+                                                       const double* __restrict__ a,
+                                                       const double* __restrict__ b, int64_t n,
+                                                       double* __restrict__ partial) {
+    constexpr int NX = 3;
+    __shared__ double sh[2 * MD_TILE + NX][4];
+    const int i0 = blockIdx.y * MD_TILE;
+    const int cnt = max(0, min(MD_TILE, k - i0));
+    const bool extras = blockIdx.y == 0;
+    double acc_a[MD_TILE], acc_b[MD_TILE], ex[NX] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < MD_TILE; ++q) { acc_a[q] = 0; acc_b[q] = 0; }
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double ae = a[e], be = b[e];
+#pragma unroll
+        for (int q = 0; q < MD_TILE; ++q) {
+            if (q < cnt) {
+                const double vi = V[(int64_t)(i0 + q) * ldv + e];
+                acc_a[q] += vi * ae;
+                acc_b[q] += vi * be;
+            }
+        }
+        if (extras) { ex[0] += ae * ae; ex[1] += ae * be; ex[2] += be * be; }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2 * MD_TILE + NX; ++q) {
+        double v = q < MD_TILE ? acc_a[q] : (q < 2 * MD_TILE ? acc_b[q - MD_TILE] : ex[q - 2 * MD_TILE]);
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) sh[q][wid] = v;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const double tot = (t < 2 * MD_TILE + NX) ? sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3] : 0.0;
+    if (t < cnt) partial[(int64_t)(i0 + t) * gridDim.x + blockIdx.x] = tot;
+    else if (t >= MD_TILE && t < MD_TILE + cnt)
+        partial[(int64_t)(k + i0 + t - MD_TILE) * gridDim.x + blockIdx.x] = tot;
+    else if (extras && t >= 2 * MD_TILE && t < 2 * MD_TILE + NX)
+        partial[(int64_t)(2 * k + t - 2 * MD_TILE) * gridDim.x + blockIdx.x] = tot;
+}
+
+// out[f] = sum of the nblk partials of slot f (one block per slot)
+__global__ __launch_bounds__(256) void k_sum_slots(const double* __restrict__ partial, int nblk,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[4];
+    const int f = blockIdx.x;
+    double acc = 0;
+    for (int e = threadIdx.x; e < nblk; e += 256) acc += partial[(int64_t)f * nblk + e];
+    const double s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) out[f] = s;
+}
+
+// Second pass of the delayed scheme: with c = V^T u and d = V^T w over the
+// k finished basis vectors (u = column k of V, the previous projected
+// vector), finish column k as v = (u - V c) / alpha and store the new
+// projected vector (w - V d - e v) / s in column k + 1.
+__global__ __launch_bounds__(256) void k_dcgs_update_t(double* __restrict__ V, int64_t ldv, int k,
+                                                       const double* __restrict__ c,
+                                                       const double* __restrict__ d,
+                                                       const double* __restrict__ w, double inv_alpha,
+                                                       double ecoef, double inv_s, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double s1 = 0, s2 = 0;
+    for (int i = 0; i < k; ++i) {
+        const double vi = V[(int64_t)i * ldv + e];
+        s1 += c[i] * vi;
+        s2 += d[i] * vi;
+    }
+    const double v = (V[(int64_t)k * ldv + e] - s1) * inv_alpha;
+    V[(int64_t)k * ldv + e] = v;
+    V[(int64_t)(k + 1) * ldv + e] = (w[e] - s2 - ecoef * v) * inv_s;
+}
+
 __global__ __launch_bounds__(256) void k_multiaxpy_t(double* __restrict__ y, const double* __restrict__ X,
                                                      int64_t ldx, int k, const double* __restrict__ c,
                                                      double alpha, int64_t n) {
@@ -889,66 +1149,92 @@ hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, 
     return apply_d<2, float>(L, form, block, mode, (const float*)x, (const float*)b, (float*)y, s);
 }
 
+static inline unsigned blocks256(int64_t threads) { return (unsigned)((threads + 255) / 256); }
+
+// One Uzawa step (eq. Uzawa_smooth) on split-layout vectors: symmetric
+// velocity sweep (forward colours 0..d, backward d..0; bulk then special
+// launch per colour), then delta = 0, pressure forward sweep on C,
+// p += omega delta.  ws holds d + 1 split fields: g = f - B^T p in fields
+// 0..d-1 during the velocity sweep, s = B u - C p - g in field 0 and delta in
+// field d during the pressure sweep.
 template <int D, int F, typename T>
-static hipError_t smooth_t(const LevelView& L, double omega, T* x, const T* b, T* work, hipStream_t s) {
-    const int64_t nb1 = interior_blocks<D>(L.n, 1);
-    const int64_t nbc = interior_blocks<D>(L.n, D + 1);
-    T* g = work;                                   // D fields: f - B^T p
-    T* sres = work;                                // field 0: B u - C p - g
-    T* delta = work + (int64_t)D * L.N;            // field D
-    // velocity: forward colours 0..D, then backward colours D..0
-    if (nb1 > 0)
-        hipLaunchKernelGGL((k_vel_rhs_bulk<D, T>), dim3((unsigned)nb1), dim3(BX, BY), 0, s, L, x, b, g);
+static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs, T* ws, hipStream_t s) {
+    const int64_t ta = split_all_threads<D>(L);
+    const int64_t tc = split_colour_threads<D>(L.n);
+    T* g = ws;
+    T* sres = ws;
+    T* delta = ws + (int64_t)D * L.Ns;
+    if (ta > 0)
+        hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3(blocks256(ta)), dim3(256), 0, s, L, xs, bs, g);
     for (int pass = 0; pass < 2; ++pass) {
         for (int cc = 0; cc <= D; ++cc) {
             const int c = pass == 0 ? cc : D - cc;
             const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
             if (pass == 0) {
-                if (nbc > 0)
-                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, false, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, g);
+                if (tc > 0)
+                    hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3(blocks256(tc)), dim3(256), 0, s, L, c, xs, g);
                 if (ns > 0)
-                    hipLaunchKernelGGL((k_gs_vel_special<D, F, false, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, x, b);
+                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs);
             } else {
-                if (nbc > 0)
-                    hipLaunchKernelGGL((k_gs_vel_bulk<D, F, true, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, x, g);
+                if (tc > 0)
+                    hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3(blocks256(tc)), dim3(256), 0, s, L, c, xs, g);
                 if (ns > 0)
-                    hipLaunchKernelGGL((k_gs_vel_special<D, F, true, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, x, b);
+                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs);
             }
         }
     }
-    // pressure: delta = 0, forward colour sweep on C, p += omega delta
-    hipLaunchKernelGGL((k_fill_t<T>), grid1(L.N), dim3(256), 0, s, delta, L.N, (T)0);
-    if (nb1 > 0)
-        hipLaunchKernelGGL((k_p_rhs_bulk<D, T>), dim3((unsigned)nb1), dim3(BX, BY), 0, s, L, x, b, sres);
+    hipLaunchKernelGGL((k_fill_t<T>), grid1(L.Ns), dim3(256), 0, s, delta, L.Ns, (T)0);
+    if (ta > 0)
+        hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3(blocks256(ta)), dim3(256), 0, s, L, xs, bs, sres);
     for (int c = 0; c <= D; ++c) {
-        if (nbc > 0)
-            hipLaunchKernelGGL((k_gs_p_bulk<D, T>), dim3((unsigned)nbc), dim3(BX, BY), 0, s, L, c, sres, delta);
+        if (tc > 0)
+            hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3(blocks256(tc)), dim3(256), 0, s, L, c, sres, delta);
         const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
         if (ns > 0)
-            hipLaunchKernelGGL((k_gs_p_special<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, x, b, delta);
+            hipLaunchKernelGGL((k_gs_p_special_s<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
     }
-    hipLaunchKernelGGL((k_axpy_field<T>), grid1(L.N), dim3(256), 0, s, x + (int64_t)D * L.N, delta,
-                       (T)omega, L.N);
+    hipLaunchKernelGGL((k_axpy_field<T>), grid1(L.Ns), dim3(256), 0, s, xs + (int64_t)D * L.Ns, delta,
+                       (T)omega, L.Ns);
     return hipGetLastError();
 }
 
 template <int D, typename T>
-static hipError_t smooth_d(const LevelView& L, int form, double omega, T* x, const T* b, T* work,
+static hipError_t smooth_d(const LevelView& L, int form, double omega, T* xs, const T* bs, T* ws,
                            hipStream_t s) {
-    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, x, b, work, s);
-    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, x, b, work, s);
-    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, x, b, work, s);
+    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, xs, bs, ws, s);
+    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, xs, bs, ws, s);
+    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, xs, bs, ws, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* x, const void* b,
-                         void* work, hipStream_t s) {
+hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs, const void* bs,
+                         void* ws, hipStream_t s) {
     if (prec == PREC_F64) {
-        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)x, (const double*)b, (double*)work, s);
-        return smooth_d<2, double>(L, form, omega, (double*)x, (const double*)b, (double*)work, s);
+        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s);
+        return smooth_d<2, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s);
     }
-    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)x, (const float*)b, (float*)work, s);
-    return smooth_d<2, float>(L, form, omega, (float*)x, (const float*)b, (float*)work, s);
+    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s);
+    return smooth_d<2, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s);
+}
+
+template <int D, typename T>
+static void split_t(const LevelView& L, int nf, const T* in, T* out, int dir, hipStream_t s) {
+    if (dir == SPLIT_PACK)
+        hipLaunchKernelGGL((k_pack_t<D, T>), dim3(blocks256(L.Ns), nf), dim3(256), 0, s, L, in, out);
+    else
+        hipLaunchKernelGGL((k_unpack_t<D, T>), dim3(blocks256(L.N), nf), dim3(256), 0, s, L, in, out);
+}
+
+hipError_t k_split(const LevelView& L, int prec, int nf, const void* in, void* out, int dir, hipStream_t s) {
+    if (nf <= 0) return hipSuccess;
+    if (prec == PREC_F64) {
+        if (L.dim == 3) split_t<3, double>(L, nf, (const double*)in, (double*)out, dir, s);
+        else split_t<2, double>(L, nf, (const double*)in, (double*)out, dir, s);
+    } else {
+        if (L.dim == 3) split_t<3, float>(L, nf, (const float*)in, (float*)out, dir, s);
+        else split_t<2, float>(L, nf, (const float*)in, (float*)out, dir, s);
+    }
+    return hipGetLastError();
 }
 
 hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf, void* rc,
@@ -1014,7 +1300,25 @@ hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int6
     const int nblk = (int)std::min<int64_t>(std::min<int64_t>(1024, cap), std::max<int64_t>(1, (n + 255) / 256));
     const int tiles = (kk + MD_TILE - 1) / MD_TILE;
     hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, tiles), dim3(256), 0, s, V, ldv, k, w, n, partial, with_self);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, kk, out);
+    hipLaunchKernelGGL(k_sum_slots, dim3(kk), dim3(256), 0, s, partial, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t k_dots2(const double* V, int64_t ldv, int k, const double* a, const double* b, int64_t n,
+                   double* partial, double* out, hipStream_t s) {
+    const int slots = 2 * k + 3;
+    const int nblk = (int)std::min<int64_t>(std::min<int64_t>(1024, 65536 / slots),
+                                            std::max<int64_t>(1, (n + 255) / 256));
+    const int tiles = std::max(1, (k + MD_TILE - 1) / MD_TILE);
+    hipLaunchKernelGGL(k_dots2_partial, dim3(nblk, tiles), dim3(256), 0, s, V, ldv, k, a, b, n, partial);
+    hipLaunchKernelGGL(k_sum_slots, dim3(slots), dim3(256), 0, s, partial, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t k_dcgs_update(double* V, int64_t ldv, int k, const double* c, const double* d, const double* w,
+                         double inv_alpha, double ecoef, double inv_s, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_dcgs_update_t, grid1(n), dim3(256), 0, s, V, ldv, k, c, d, w, inv_alpha, ecoef,
+                       inv_s, n);
     return hipGetLastError();
 }
 

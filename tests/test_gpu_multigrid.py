@@ -172,6 +172,23 @@ def test_vcycle_default_configuration(name, levels):
     P.close()
 
 
+def test_vcycle_variable_smoothing():
+    """V_var: two more smoothing steps per coarser level, against the
+    oracle hierarchy with the same schedule."""
+    w = small_workload("sphere_3d", 4)
+    P = gpu_problem(w, coarse_mu="average", coarse_form="strain", omega=0.6, nu1=2, nu2=3, nu_inc=2)
+    H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"],
+                     "interface", nu1=2, nu2=3, omega=0.6, coarse_mu="average", coarse_form="strain",
+                     nu_inc=2)
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=33)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=34)
+    xg = to_dev(x)
+    P.vcycle("interface", xg, to_dev(b))
+    ref = H.vcycle(w["levels"], x, b)
+    assert _rel(to_host(xg), ref) < 1e-10
+    P.close()
+
+
 def test_buoyancy_solve_full_pipeline():
     """RHS from the library's buoyancy kernel, FGMRES with the benchmark's
     V-cycle configuration; checked against the oracle's buoyancy load and
