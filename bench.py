@@ -15,6 +15,7 @@ same solver.
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -36,8 +37,8 @@ def parse():
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--omega", type=float, default=0.6)
-    ap.add_argument("--nu", type=int, default=5, help="pre- and post-smoothing steps")
-    ap.add_argument("--nu-inc", type=int, default=0,
+    ap.add_argument("--nu", type=int, default=4, help="pre- and post-smoothing steps")
+    ap.add_argument("--nu-inc", type=int, default=2,
                     help="variable V-cycle: extra smoothing steps per level below the finest")
     ap.add_argument("--restart", type=int, default=150)
     ap.add_argument("--maxit", type=int, default=400)
@@ -94,9 +95,9 @@ x, h = mg.solve_fgmres(H, b, rtol=1e-8, restart=%d, maxit=%d)
 dt = time.time() - t
 print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h[-1])}))
 """
-    lv_small = min(w["levels"], 4)
+    lv_small = min(w["levels"], 5)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, nu_inc, restart, 25)
+    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, nu_inc, restart, 20)
     out = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, env=env, timeout=600)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
@@ -108,6 +109,26 @@ print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h
             "sample": "oracle FGMRES + Uzawa V-cycle (same settings) on %s refined %d times (%d vertices), %d iterations "
                       "in %.1f s, scaled by vertex count to %d vertices and to the GPU's %d "
                       "iterations" % (w["name"], lv_small, r["N"], r["its"], r["seconds"], N_full, its_gpu)}
+
+
+def measured_traffic(kernel, form):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a plain copy of known size), or None when the kernel source
+    has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_1604_07994_amd", "csrc", "iss_kernels.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    entry = rec.get("%s/%s" % (kernel, form))
+    if not entry or rec.get("iss_kernels_sha256") != digest:
+        return None
+    return entry["bytes_per_launch"]
 
 
 def learned_report(seeds=(100000, 100004)):
@@ -219,27 +240,32 @@ def main():
                                                        "bytes_per_vertex": bpv}
         for form in forms:
             xs = torch.zeros_like(b)
-            smooth_ms[form] = event_time(lambda: P.smooth(form, xs, b, 1), 5)
+            P.smooth(form, xs, b, 1)
+            phase, step = P.smooth_timed(form, xs, b, 5)
+            smooth_ms[form] = {"velocity_colour_phase_ms": phase, "step_ms": step}
         log("apply GB/s: %s" % {k: round(v["GBs"], 1) for k, v in apply_gbs.items()})
-        log("smoothing step ms: %s" % smooth_ms)
+        log("smoothing (HIP events): %s" % smooth_ms)
 
     main_form = forms[0]
     value = results[main_form]["seconds"]
-    # roofline: the velocity Gauss-Seidel colour phase is the kernel with the
-    # most time in a solve; one smoothing step = 2 (d+1) velocity phases +
-    # (d+1) pressure phases.  Algorithmic bytes of a smoothing step per
-    # vertex: symmetric velocity sweep 2 x 81 B + pressure step 49 B.
+    # roofline of the dominant kernel: the bulk velocity Gauss-Seidel colour
+    # phase (k_gs_vel_s; the largest kernel-time share of a solve).  One
+    # launch updates the interior isoviscous vertices of one colour class;
+    # it must read the three velocity fields on the two neighbouring colour
+    # classes (2 x 24 B per class vertex), g = f - B^T p (24 B) and the phase
+    # byte on its own class, and write its class (24 B): 97 B per class
+    # vertex, i.e. 97 / 4 B per interior lattice vertex.
     roof = None
     if smooth_ms:
-        bytes_step = (2 * 81 + 49) * N
-        ach = bytes_step / (smooth_ms[main_form] * 1e-3) / 1e9
+        n_int = (w["n"] - 1) ** w["dim"]
+        bytes_launch = 97.0 / (w["dim"] + 1) * n_int
+        ms = smooth_ms[main_form]["velocity_colour_phase_ms"]
+        ach = bytes_launch / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm",
-                "kernel": "one Uzawa smoothing step, finest level, %s form (1 rhs + 8 velocity colour "
-                          "phases + 1 rhs + 4 pressure colour phases + 2 vector kernels)" % main_form,
-                "algorithmic_bytes": bytes_step, "bytes_per_vertex": 2 * 81 + 49,
-                "ms": smooth_ms[main_form],
-                "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                "traffic": None}
+                "kernel": "k_gs_vel_s (%s form, bulk velocity colour phase, finest level, FP64)" % main_form,
+                "algorithmic_bytes_per_launch": bytes_launch, "bytes_per_class_vertex": 97,
+                "ms_per_launch": ms, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic("k_gs_vel_s", main_form)}
     cpu = None
     if not args.no_cpu:
         try:

@@ -170,6 +170,14 @@ int iss_residual(iss_problem* p, int form, int level, int prec, const void* x,
 int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps,
                void* x, const void* b, iss_stream_t stream);
 
+/* Same as iss_smooth, for measurement: HIP events recorded on `stream`
+ * around every bulk velocity colour-phase launch and around every step.
+ * ms[0] receives the average duration of one bulk velocity colour-phase
+ * launch (interior isoviscous vertices of one colour class), ms[1] the
+ * average duration of one whole step, in milliseconds.  Synchronises. */
+int iss_smooth_timed(iss_problem* p, int form, int level, int prec, int nsteps,
+                     void* x, const void* b, iss_stream_t stream, double* ms);
+
 /* Grid transfers between `level` (fine) and level-1: restriction
  * rc = P^T rf (velocity zero on coarse boundary vertices) and
  * xf += P ec, P = P1 interpolation between the nested lattices. */

@@ -48,7 +48,7 @@ EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "
            "iss_dot", "iss_last_error", "iss_net_create", "iss_net_destroy", "iss_net_info",
            "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
            "iss_net_targets", "iss_net_backward", "iss_adam_step", "iss_problem_set_net",
-           "iss_net_correction", "iss_net_output_grad"]
+           "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed"]
 
 
 def lib():
@@ -77,6 +77,7 @@ def lib():
     L.iss_apply.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
     L.iss_residual.argtypes = [vp, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl), vp]
     L.iss_smooth.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
+    L.iss_smooth_timed.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl)]
     L.iss_restrict.argtypes = [vp, cint, cint, vp, vp, vp]
     L.iss_prolong_add.argtypes = [vp, cint, cint, vp, vp, vp]
     L.iss_coarse_solve.argtypes = [vp, cint, vp, vp, vp]
@@ -224,6 +225,15 @@ class Problem:
         _check(lib().iss_smooth(self._h, FORMS[form], level, _prec(x), nsteps,
                                 self._vec(x, level), self._vec(b, level), _stream()))
         return x
+
+    def smooth_timed(self, form, x, b, nsteps=1, level=None):
+        """iss_smooth with HIP-event timing: returns (average bulk velocity
+        colour-phase launch, average step) in milliseconds."""
+        level = self.levels if level is None else level
+        ms = (ctypes.c_double * 2)()
+        _check(lib().iss_smooth_timed(self._h, FORMS[form], level, _prec(x), nsteps,
+                                      self._vec(x, level), self._vec(b, level), _stream(), ms))
+        return ms[0], ms[1]
 
     def restrict(self, rf, rc, level=None):
         level = self.levels if level is None else level

@@ -100,6 +100,101 @@ template <> struct Kuhn<2> {
     static constexpr KuhnTables<2> T = detail::make_tables<2>();
 };
 
+// Barycentric gradients of the unit Kuhn simplices.  For the simplex
+// 0, e_p0, e_p0 + e_p1, ... the coordinates are lambda_0 = 1 - x_p0,
+// lambda_s = x_p(s-1) - x_ps, lambda_d = x_p(d-1), so every gradient is an
+// integer vector with entries in {-1, 0, 1} and the element volume is 1/d!.
+// The element matrices below are therefore exact rationals known at compile
+// time; the special-vertex kernels fold them into immediates instead of
+// reading tables.
+template <int D>
+struct KuhnGrads {
+    int g[KuhnTables<D>::NT][D + 1][3];
+};
+
+namespace detail {
+template <int D>
+constexpr KuhnGrads<D> make_grads() {
+    KuhnGrads<D> r{};
+    constexpr auto& K = Kuhn<D>::T;
+    for (int ty = 0; ty < KuhnTables<D>::NT; ++ty) {
+        int ax[3] = {0, 0, 0};
+        for (int s = 0; s < D; ++s)
+            for (int a = 0; a < 3; ++a)
+                if (K.type_vert[ty][s + 1][a] - K.type_vert[ty][s][a] == 1) ax[s] = a;
+        for (int v = 0; v <= D; ++v)
+            for (int a = 0; a < 3; ++a) r.g[ty][v][a] = 0;
+        r.g[ty][0][ax[0]] = -1;
+        for (int s = 1; s < D; ++s) {
+            r.g[ty][s][ax[s - 1]] += 1;
+            r.g[ty][s][ax[s]] -= 1;
+        }
+        r.g[ty][D][ax[D - 1]] = 1;
+    }
+    return r;
+}
+}  // namespace detail
+
+template <int D> struct KGrad { static constexpr KuhnGrads<D> G = detail::make_grads<D>(); };
+
+// unit-lattice element volume 1/d!
+template <int D> constexpr double kuhn_volume() { return D == 3 ? 1.0 / 6.0 : 0.5; }
+
+// integer part of the element matrices (times the volume): test phi_a e_l,
+// trial phi_b e_k of element type ty
+template <int D>
+constexpr int kg_dot(int ty, int a, int b) {
+    int s = 0;
+    for (int q = 0; q < D; ++q) s += KGrad<D>::G.g[ty][a][q] * KGrad<D>::G.g[ty][b][q];
+    return s;
+}
+// form 0: (grad, grad); 1: 2 (sym grad, sym grad); 2: 1 minus (div, div)
+template <int D>
+constexpr int kg_visc(int form, int ty, int a, int l, int b, int k) {
+    const auto& g = KGrad<D>::G.g[ty];
+    const int lap = (k == l) ? kg_dot<D>(ty, a, b) : 0;
+    if (form == 0) return lap;
+    const int sym = lap + g[b][l] * g[a][k];
+    if (form == 1) return sym;
+    return sym - g[b][k] * g[a][l];
+}
+
+// Integer parts of the stencils of an isoviscous interior vertex (sums of
+// the element entries over the incident elements): the divergence row B
+// (times -|T|/(d+1)), its transpose B^T (same factor) and C (times |T|).
+template <int D>
+constexpr int sdiv_int(int k, int o) {
+    constexpr auto& K = Kuhn<D>::T;
+    int s = 0;
+    for (int sl = 0; sl < KuhnTables<D>::NS; ++sl)
+        for (int b = 0; b <= D; ++b)
+            if (K.slot_nb[sl][b] == o) s += KGrad<D>::G.g[K.slot_type[sl]][b][k];
+    return s;
+}
+template <int D>
+constexpr int sbt_int(int l, int o) {
+    constexpr auto& K = Kuhn<D>::T;
+    int s = 0;
+    for (int sl = 0; sl < KuhnTables<D>::NS; ++sl)
+        for (int b = 0; b <= D; ++b)
+            if (K.slot_nb[sl][b] == o) s += KGrad<D>::G.g[K.slot_type[sl]][K.slot_loc[sl]][l];
+    return s;
+}
+template <int D>
+constexpr int sc_int(int o) {
+    constexpr auto& K = Kuhn<D>::T;
+    int s = 0;
+    for (int sl = 0; sl < KuhnTables<D>::NS; ++sl)
+        for (int b = 0; b <= D; ++b)
+            if (K.slot_nb[sl][b] == o) s += kg_dot<D>(K.slot_type[sl], K.slot_loc[sl], b);
+    return s;
+}
+// footprint index of the offset (dx, dy, dz), or -1
+template <int D>
+constexpr int off_index(int dx, int dy, int dz) {
+    return detail::find_off<D>(Kuhn<D>::T, dx, dy, dz);
+}
+
 // Floating-point element tables for the unit lattice (h = 1); per level the
 // viscous block scales with h^(d-2), B with h^(d-1) and C with beta h^d.
 //   Avis[f][type][a*D+l][b*D+k]: viscous form f (0 gradient, 1 strain,

@@ -80,6 +80,13 @@ int build_tables(ElemTables<D, double>& t) {
             for (int a = 0; a < 3; ++a) X[b][a] = K.type_vert[ty][b][a];
         double g[D + 1][D], vol;
         simplex_gradients<D>(X, g, vol);
+        // the kernels use the exact integer gradients of iss_geometry.h
+        if (std::fabs(vol - kuhn_volume<D>()) > 1e-15)
+            return fail(ISS_E_INVAL, "geometry table: Kuhn simplex volume");
+        for (int b = 0; b <= D; ++b)
+            for (int q = 0; q < D; ++q)
+                if (std::fabs(g[b][q] - KGrad<D>::G.g[ty][b][q]) > 1e-13)
+                    return fail(ISS_E_INVAL, "geometry table: Kuhn gradients");
         for (int a = 0; a <= D; ++a)          // test vertex
             for (int b = 0; b <= D; ++b) {    // trial vertex
                 double gg = 0;
@@ -130,6 +137,17 @@ int build_tables(ElemTables<D, double>& t) {
             }
     for (int o = 2 * D + 1; o < NB; ++o)
         if (std::fabs(t.Sc[o]) > 1e-13) return fail(ISS_E_INVAL, "C stencil not axis-only");
+    // the right-hand-side kernels use the compile-time integer stencils
+    const double vol = kuhn_volume<D>(), bvol = -vol / (D + 1);
+    for (int o = 0; o < NB; ++o) {
+        if (std::fabs(t.Sc[o] - vol * sc_int<D>(o)) > 1e-13) return fail(ISS_E_INVAL, "C stencil (integer form)");
+        for (int k = 0; k < D; ++k) {
+            if (std::fabs(t.Sdiv[k][o] - bvol * sdiv_int<D>(k, o)) > 1e-13)
+                return fail(ISS_E_INVAL, "B stencil (integer form)");
+            if (std::fabs(t.Sbt[k][o] - bvol * sbt_int<D>(k, o)) > 1e-13)
+                return fail(ISS_E_INVAL, "B^T stencil (integer form)");
+        }
+    }
     return ISS_OK;
 }
 
@@ -278,7 +296,10 @@ void centroid_phases(iss_problem* p, int l) {
             L.elem_phase[c * NT + ty] = (uint8_t)element_phase(p, cen);
         }
     }
-    L.mu_tab.assign(p->mu.begin(), p->mu.end());
+    // 256 entries: every phase byte, including the unused ones and the
+    // OUTSIDE / SPECIAL marker 255, indexes a defined entry
+    L.mu_tab.assign(256, 1.0);
+    std::copy(p->mu.begin(), p->mu.end(), L.mu_tab.begin());
     L.imu_tab.resize(256);
     for (int i = 0; i < 256; ++i) L.imu_tab[i] = 1.0 / L.mu_tab[i];
 }
@@ -421,8 +442,8 @@ int setup_level(iss_problem* p, int l) {
     std::vector<uint8_t> vphase(N);
     L.cls.assign(N, 0);
     std::vector<uint8_t> slotph((size_t)N * 0);   // built only for special vertices below
-    std::vector<std::vector<int32_t>> spec_by_col(D + 1);
-    std::vector<std::vector<uint8_t>> eph_by_col(D + 1);
+    std::vector<std::vector<int32_t>> spec_by_col(2 * (D + 1));   // [colour] boundary, [D+1+colour] interior
+    std::vector<std::vector<uint8_t>> eph_by_col(2 * (D + 1));
     int64_t nif = 0, nbd = 0;
     const int nthr = 1;
     (void)nthr;
@@ -454,7 +475,9 @@ int setup_level(iss_problem* p, int l) {
         if (bnd) { L.cls[v] |= 2; ++nbd; }
         if (bnd || mixed_phase) {
             vphase[v] = SPECIAL;
-            const int col = (i + j + k) % (D + 1);
+            // per colour: boundary vertices first, then interior ones, so
+            // that waves of the special kernels mostly take one path
+            const int col = (i + j + k) % (D + 1) + (bnd ? 0 : D + 1);
             spec_by_col[col].push_back((int32_t)v);
             eph_by_col[col].insert(eph_by_col[col].end(), ph, ph + NS);
         } else {
@@ -468,8 +491,10 @@ int setup_level(iss_problem* p, int l) {
     int64_t off[5] = {0, 0, 0, 0, 0};
     for (int c = 0; c <= D; ++c) {
         off[c] = (int64_t)spec.size();
-        spec.insert(spec.end(), spec_by_col[c].begin(), spec_by_col[c].end());
-        eph.insert(eph.end(), eph_by_col[c].begin(), eph_by_col[c].end());
+        for (int part : {c, D + 1 + c}) {
+            spec.insert(spec.end(), spec_by_col[part].begin(), spec_by_col[part].end());
+            eph.insert(eph.end(), eph_by_col[part].begin(), eph_by_col[part].end());
+        }
     }
     for (int c = D + 1; c < 5; ++c) off[c] = (int64_t)spec.size();
     if (l == p->levels) {
@@ -1219,6 +1244,61 @@ int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps, void* 
     for (int i = 0; i < nsteps; ++i)
         ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
     ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
+    return ISS_OK;
+}
+
+int iss_smooth_timed(iss_problem* p, int form, int level, int prec, int nsteps, void* x, const void* b,
+                     iss_stream_t stream, double* ms) {
+    if (!p || !x || !b || !ms || nsteps < 1) return fail(ISS_E_INVAL, "bad argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    if ((rc = ensure_work(p, level, prec))) return rc;
+    Level& L = p->lv[level];
+    const hipStream_t s = (hipStream_t)stream;
+    const int nf = p->dim + 1, nph = 2 * nf;
+    void *xs, *bs, *ws;
+    split_buffers(p, level, prec, &xs, &bs, &ws);
+    PhaseTimer tm{};
+    hipEvent_t st0 = nullptr, st1 = nullptr;
+    auto cleanup = [&]() {
+        for (int q = 0; q < 8; ++q) {
+            if (tm.begin[q]) (void)hipEventDestroy(tm.begin[q]);
+            if (tm.end[q]) (void)hipEventDestroy(tm.end[q]);
+        }
+        if (st0) (void)hipEventDestroy(st0);
+        if (st1) (void)hipEventDestroy(st1);
+    };
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < nph && e == hipSuccess; ++q) {
+        e = hipEventCreate(&tm.begin[q]);
+        if (e == hipSuccess) e = hipEventCreate(&tm.end[q]);
+    }
+    if (e == hipSuccess) e = hipEventCreate(&st0);
+    if (e == hipSuccess) e = hipEventCreate(&st1);
+    if (e != hipSuccess) { cleanup(); return fail(ISS_E_HIP, hipGetErrorString(e)); }
+    double phase_ms = 0, step_ms = 0;
+    int nphase = 0;
+    e = k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s);
+    if (e == hipSuccess) e = k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s);
+    for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
+        e = hipEventRecord(st0, s);
+        if (e == hipSuccess) e = k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s, &tm);
+        if (e == hipSuccess) e = hipEventRecord(st1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(st1);
+        float t = 0;
+        for (int q = 0; q < nph && e == hipSuccess; ++q) {
+            e = hipEventElapsedTime(&t, tm.begin[q], tm.end[q]);
+            phase_ms += t;
+            ++nphase;
+        }
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, st0, st1);
+        step_ms += t;
+    }
+    if (e == hipSuccess) e = k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s);
+    cleanup();
+    if (e != hipSuccess) return fail(ISS_E_HIP, hipGetErrorString(e));
+    ms[0] = phase_ms / std::max(1, nphase);
+    ms[1] = step_ms / nsteps;
     return ISS_OK;
 }
 

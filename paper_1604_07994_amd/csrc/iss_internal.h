@@ -49,10 +49,15 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
                          size_t bytes32);
 hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec,
                    const void* x, const void* b, void* y, hipStream_t s);
+// events around the 2 (d+1) bulk velocity colour-phase launches of a step
+struct PhaseTimer {
+    hipEvent_t begin[8], end[8];
+};
 // one Uzawa step on split-layout vectors xs, bs (d+1 fields of Ns each);
-// ws holds d+1 split fields of scratch
+// ws holds d+1 split fields of scratch; tm (optional) times the bulk
+// velocity colour phases
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs,
-                         const void* bs, void* ws, hipStream_t s);
+                         const void* bs, void* ws, hipStream_t s, PhaseTimer* tm = nullptr);
 // canonical <-> split copy of nf fields (dir SPLIT_PACK: canonical in, split
 // out with zero padding; SPLIT_UNPACK: split in, canonical out)
 hipError_t k_split(const LevelView& L, int prec, int nf, const void* in, void* out, int dir,

@@ -67,50 +67,50 @@ template <> struct PrecU<float> {
 
 // Spread consecutive workgroups over the 8 XCDs in contiguous chunks: the
 // dispatcher sends workgroup b to XCD b % 8, so remapping makes every XCD
-// walk one contiguous slab of the lattice and keeps stencil halos in its
-// own L2.
+// walk one contiguous range of the linear work order (used by the 1D
+// vector kernels).
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
     const int64_t x = b & 7, idx = b >> 3;
     const int64_t per = nb >> 3, rem = nb & 7;
     return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
 }
 
+// Stencil kernels split the interior rows j = 1..m into 8 slabs of
+// ceil(m / 8) rows, one per XCD (workgroup b runs on XCD b % 8), and walk
+// each slab in the order x, then y inside the slab, then z.  An XCD then
+// works on a narrow band of a few planes at a time, so the rows and planes
+// around a vertex are still in its own L2 when they are read again.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int slab_rows(int m) { return (m + NXCD - 1) / NXCD; }
+inline int slab_rows_h(int m) { return (m + NXCD - 1) / NXCD; }
+
 constexpr int BX = 64, BY = 4;   // 256-thread workgroups: 64 along x, 4 rows
 
-// Interior vertex (1..n-1 per axis) of a bulk kernel; `step` > 1 walks one
-// colour class along x.  Returns false for threads past the row end.
+// Interior vertex (1..n-1 per axis) of a bulk kernel (64 x 4 tiles inside
+// the XCD's slab).  Returns false for threads outside the interior.
 template <int D>
-__device__ __forceinline__ bool interior_vertex(const LevelView& L, int colour, int step, int64_t bid,
-                                                int& i, int& j, int& k) {
+__device__ __forceinline__ bool interior_vertex(const LevelView& L, int64_t bid, int& i, int& j, int& k) {
     const int m = L.n - 1;                       // interior points per axis
-    const int cnt = (step == 1) ? m : (m + step - 1) / step;
-    const int gx = (cnt + BX - 1) / BX, gy = (m + BY - 1) / BY;
-    const int64_t nb = (int64_t)gx * gy * (D == 3 ? m : 1);
-    const int64_t b = xcd_remap(bid, nb);
-    const int bx = (int)(b % gx);
-    const int64_t r = b / gx;
-    const int by = (int)(r % gy);
-    k = (D == 3) ? 1 + (int)(r / gy) : 0;
-    j = 1 + by * BY + (int)threadIdx.y;
-    if (j > m) return false;
-    const int t = bx * BX + (int)threadIdx.x;
-    if (step == 1) {
-        i = 1 + t;
-    } else {
-        int i0 = (colour - j - k) % step;
-        if (i0 < 0) i0 += step;
-        if (i0 == 0) i0 = step;                   // first i >= 1 in the class
-        i = i0 + step * t;
-    }
-    return i <= m;
+    const int rows = slab_rows(m);
+    const int gx = (m + BX - 1) / BX, gys = (rows + BY - 1) / BY;
+    const int xcd = (int)(bid & (NXCD - 1));
+    const int64_t idx = bid / NXCD;
+    const int bx = (int)(idx % gx);
+    const int64_t r = idx / gx;
+    const int by = (int)(r % gys);
+    k = (D == 3) ? 1 + (int)(r / gys) : 0;
+    const int jl = by * BY + (int)threadIdx.y;
+    j = 1 + xcd * rows + jl;
+    i = 1 + bx * BX + (int)threadIdx.x;
+    return jl < rows && j <= m && i <= m && (D == 2 || k <= m);
 }
 
 template <int D>
-inline int64_t interior_blocks(int n, int step) {
+inline int64_t interior_blocks(int n) {
     const int m = n - 1;
     if (m <= 0) return 0;
-    const int cnt = (step == 1) ? m : (m + step - 1) / step;
-    return (int64_t)((cnt + BX - 1) / BX) * ((m + BY - 1) / BY) * (D == 3 ? m : 1);
+    const int rows = slab_rows_h(m);
+    return (int64_t)NXCD * ((m + BX - 1) / BX) * ((rows + BY - 1) / BY) * (D == 3 ? m : 1);
 }
 
 template <int D>
@@ -134,25 +134,29 @@ __device__ __forceinline__ void load_interior(const LevelView& L, const T* __res
 }
 
 // guarded load for vertices that may sit on the boundary
+// compile-time loop: fn(integral_constant<int, i>) for i = I..N-1
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(fn);
+    }
+}
+
 template <int D, int NF, typename T, typename C>
 __device__ __forceinline__ void load_guarded(const LevelView& L, const T* __restrict__ x,
                                              int64_t v, const int (&ijk)[3], int f0,
                                              C (&V)[NF][KuhnTables<D>::NB]) {
-    constexpr auto& TT = Kuhn<D>::T;
-    constexpr int NB = KuhnTables<D>::NB;
-#pragma unroll
-    for (int o = 0; o < NB; ++o) {
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int c = ijk[a] + TT.off[o][a];
-            in = in && (c >= 0) && (c <= L.n);
-        }
-        const int64_t nv = v + nb_lin<D>(L, o);
+    static_for<0, KuhnTables<D>::NB>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
+        const bool in = (ijk[0] + dx >= 0) && (ijk[0] + dx <= L.n) && (ijk[1] + dy >= 0) &&
+                        (ijk[1] + dy <= L.n) && (D == 2 || ((ijk[2] + dz >= 0) && (ijk[2] + dz <= L.n)));
+        const int64_t nv = v + dx + (int64_t)dy * L.sy + (int64_t)dz * L.sz;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
             V[f][o] = in ? (C)x[(int64_t)(f0 + f) * L.N + nv] : (C)0;
-    }
+    });
 }
 
 template <int D>
@@ -186,16 +190,12 @@ struct RowAcc {
     C cjj;            // point diagonal of sum_T (1/mu_T) C_T
 };
 
-template <int I, int N, typename Fn>
-__device__ __forceinline__ void static_for(Fn&& fn) {
-    if constexpr (I < N) {
-        fn(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(fn);
-    }
-}
-
-// The slot and vertex loops are unrolled at compile time, so every index
-// into the preloaded footprint arrays is a constant (registers, no scratch).
+// The slot, vertex and component loops are unrolled at compile time: every
+// index into the preloaded footprint arrays is a constant (registers, no
+// scratch), and every element-matrix entry is an integer known at compile
+// time (exact Kuhn gradients; the common factors |T| and -|T|/(d+1) are
+// applied once at the end), so zero entries cost nothing and no table is
+// read.
 template <int D, int F, bool VEL, bool PRES, bool WANT_D, bool WANT_DELTA, typename C>
 __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
                                              const C (&U)[D][KuhnTables<D>::NB],
@@ -203,7 +203,8 @@ __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
                                              const C (&Dl)[KuhnTables<D>::NB],
                                              RowAcc<D, F, VEL, PRES, C>& r) {
     constexpr int NS = KuhnTables<D>::NS;
-    const auto& E = ETab<D, C>::get();
+    constexpr C VOL = (C)kuhn_volume<D>();
+    constexpr C BVOL = (C)(-kuhn_volume<D>() / (D + 1));
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         r.au[a] = 0; r.abt[a] = 0;
@@ -211,46 +212,95 @@ __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
         for (int b = 0; b < D; ++b) r.Dm[a][b] = 0;
     }
     r.bdiv = 0; r.cp = 0; r.cd = 0; r.cjj = 0;
-    const uint8_t* eph = L.spec_eph + s * NS;
+    // phases of all incident elements first (one batch of loads), then the
+    // viscosities; an element outside the domain contributes with weight 0
+    int ph[NS];
+    {
+        const uint8_t* eph = L.spec_eph + s * NS;
+        if constexpr (NS % 4 == 0) {
+            const uint32_t* e32 = reinterpret_cast<const uint32_t*>(eph);   // 3D: 24 bytes, 8-aligned
+#pragma unroll
+            for (int q = 0; q < NS / 4; ++q) {
+                const uint32_t wd = e32[q];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) ph[4 * q + t] = (int)((wd >> (8 * t)) & 0xffu);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) ph[q] = eph[q];
+        }
+    }
+    C inw[NS], muv[NS], imuv[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        inw[q] = ph[q] != OUTSIDE ? (C)1 : (C)0;
+        if constexpr (VEL) muv[q] = inw[q] * Prec<C>::mu(L, ph[q]);
+        if constexpr (PRES) imuv[q] = inw[q] * Prec<C>::imu(L, ph[q]);
+    }
     static_for<0, NS>([&](auto slc) {
         constexpr int sl = decltype(slc)::value;
-        const int ph = eph[sl];
-        if (ph == OUTSIDE) return;
         constexpr int ty = Kuhn<D>::T.slot_type[sl];
         constexpr int a = Kuhn<D>::T.slot_loc[sl];
-        const C mu = Prec<C>::mu(L, ph);
-        const C imu = Prec<C>::imu(L, ph);
-        static_for<0, D + 1>([&](auto bc) {
-            constexpr int bb = decltype(bc)::value;
-            constexpr int o = Kuhn<D>::T.slot_nb[sl][bb];
-            if constexpr (VEL) {
+        if constexpr (VEL) {
+            const C mu = muv[sl];
+            C au[D], psum = 0;
 #pragma unroll
-                for (int l = 0; l < D; ++l) {
-                    C acc = 0;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) acc += E.Avis[F][ty][a * D + l][bb * D + k] * U[k][o];
-                    r.au[l] += mu * acc;
-                    r.abt[l] += E.Bel[ty][bb][a * D + l] * P[o];
+            for (int l = 0; l < D; ++l) au[l] = 0;
+            static_for<0, D + 1>([&](auto bc) {
+                constexpr int bb = decltype(bc)::value;
+                constexpr int o = Kuhn<D>::T.slot_nb[sl][bb];
+                psum += P[o];
+                static_for<0, D>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    static_for<0, D>([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        constexpr int A = kg_visc<D>(F, ty, a, l, bb, k);
+                        if constexpr (A != 0) au[l] += (C)A * U[k][o];
+                        if constexpr (WANT_D && bb == a && A != 0) r.Dm[l][k] += mu * (C)A;
+                    });
+                });
+            });
+            static_for<0, D>([&](auto lc) {
+                constexpr int l = decltype(lc)::value;
+                r.au[l] += mu * au[l];
+                constexpr int ga = KGrad<D>::G.g[ty][a][l];
+                if constexpr (ga != 0) r.abt[l] += (C)ga * (inw[sl] * psum);
+            });
+        }
+        if constexpr (PRES) {
+            const C imu = imuv[sl];
+            C bd = 0, cp = 0, cd = 0;
+            static_for<0, D + 1>([&](auto bc) {
+                constexpr int bb = decltype(bc)::value;
+                constexpr int o = Kuhn<D>::T.slot_nb[sl][bb];
+                static_for<0, D>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    constexpr int gb = KGrad<D>::G.g[ty][bb][k];
+                    if constexpr (gb != 0) bd += (C)gb * U[k][o];
+                });
+                constexpr int cg = kg_dot<D>(ty, a, bb);
+                if constexpr (cg != 0) {
+                    cp += (C)cg * P[o];
+                    if constexpr (WANT_DELTA) cd += (C)cg * Dl[o];
                 }
-                if constexpr (WANT_D && bb == a) {
-#pragma unroll
-                    for (int l = 0; l < D; ++l)
-#pragma unroll
-                        for (int k = 0; k < D; ++k)
-                            r.Dm[l][k] += mu * E.Avis[F][ty][a * D + l][a * D + k];
-                }
-            }
-            if constexpr (PRES) {
-                C acc = 0;
-#pragma unroll
-                for (int k = 0; k < D; ++k) acc += E.Bel[ty][a][bb * D + k] * U[k][o];
-                r.bdiv += acc;
-                r.cp += imu * E.Cel[ty][a][bb] * P[o];
-                if constexpr (WANT_DELTA) r.cd += imu * E.Cel[ty][a][bb] * Dl[o];
-                if constexpr (WANT_D && bb == a) r.cjj += imu * E.Cel[ty][a][a];
-            }
-        });
+            });
+            r.bdiv += inw[sl] * bd;
+            r.cp += imu * cp;
+            if constexpr (WANT_DELTA) r.cd += imu * cd;
+            if constexpr (WANT_D) r.cjj += imu * (C)kg_dot<D>(ty, a, a);
+        }
     });
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        r.au[l] *= VOL;
+        r.abt[l] *= BVOL;
+#pragma unroll
+        for (int k = 0; k < D; ++k) r.Dm[l][k] *= VOL;
+    }
+    r.bdiv *= BVOL;
+    r.cp *= VOL;
+    r.cd *= VOL;
+    r.cjj *= VOL;
 }
 
 // ----------------------------------------------------------------------------
@@ -262,7 +312,7 @@ __device__ __forceinline__ void apply_bulk_body(const LevelView& L, int64_t bid,
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
     int i, j, k;
-    if (!interior_vertex<D>(L, 0, 1, bid, i, j, k)) return;
+    if (!interior_vertex<D>(L, bid, i, j, k)) return;
     const int64_t v = i + j * L.sy + k * L.sz;
     const int ph = L.vphase[v];
     if (ph == SPECIAL) return;
@@ -347,6 +397,31 @@ __device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s
     int ijk[3];
     vertex_ijk<D>(L, v, ijk);
     const bool bnd = on_boundary<D>(L, ijk);
+    if (bnd) {
+        // Dirichlet velocity rows are zero; only the (truncated) pressure
+        // row of the full operator is formed
+        C out[D + 1];
+#pragma unroll
+        for (int l = 0; l < D; ++l) out[l] = 0;
+        out[D] = 0;
+        if (BLK == BLOCK_FULL) {
+            C U[D][NB], P[1][NB];
+            load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
+            load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
+            RowAcc<D, F, false, true, C> r;
+            element_rows<D, F, false, true, false, false, C>(L, s, U, P[0], P[0], r);
+            out[D] = (C)L.sB * r.bdiv - (C)L.sC * r.cp;
+        }
+#pragma unroll
+        for (int f = 0; f <= D; ++f) {
+            const int64_t e = (int64_t)f * L.N + v;
+            if (MODE == MODE_RESID)
+                y[e] = (f == D && BLK == BLOCK_FULL) ? (T)(b[e] - out[f]) : (T)0;
+            else
+                y[e] = (T)out[f];
+        }
+        return;
+    }
     C U[D][NB], P[1][NB];
     load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
     load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
@@ -424,29 +499,38 @@ __device__ __forceinline__ int64_t snb(const LevelView& L, const XOff& xo, int o
            (int64_t)T.off[o][2] * L.Pp;
 }
 
-__device__ __forceinline__ int64_t split_thread() {
-    return xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+// Split-layout passes: the threads of XCD x cover its slab of interior rows
+// with run positions fastest, then rows, then planes.  `per_row` is the
+// number of positions per row the pass visits.  Returns false past the end.
+template <int D>
+__device__ __forceinline__ bool split_slab_thread(const LevelView& L, int per_row, int& pos, int& j, int& k) {
+    const int m = L.n - 1;
+    const int rows = slab_rows(m);
+    const int xcd = (int)(blockIdx.x & (NXCD - 1));
+    const int64_t g = (int64_t)(blockIdx.x / NXCD) * 256 + threadIdx.x;
+    pos = (int)(g % per_row);
+    const int64_t r = g / per_row;
+    const int jl = (int)(r % rows);
+    k = (D == 3) ? 1 + (int)(r / rows) : 0;
+    j = 1 + xcd * rows + jl;
+    return j <= m && (D == 3 ? k <= m : r < rows);
 }
 
-// thread g of a colour phase -> interior vertex of that colour (run s)
 template <int D>
-__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int64_t g, int& s,
-                                                    int64_t& v) {
+inline int64_t split_slab_blocks(int n, int per_row) {
+    const int m = n - 1;
+    if (m <= 0) return 0;
+    const int64_t per_xcd = (int64_t)per_row * slab_rows_h(m) * (D == 3 ? m : 1);
+    return NXCD * ((per_xcd + 255) / 256);
+}
+
+// colour phase: interior vertex of colour `colour` (run s of its row)
+template <int D>
+__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int& s, int64_t& v) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
-    const int tr = m / M + 1;                    // run positions covering i = 1..m
-    const int t = (int)(g % tr);
-    const int64_t row = g / tr;
-    int j, k;
-    if (D == 3) {
-        j = 1 + (int)(row % m);
-        k = 1 + (int)(row / m);
-        if (k > m) return false;
-    } else {
-        j = 1 + (int)row;
-        k = 0;
-        if (j > m) return false;
-    }
+    int t, j, k;
+    if (!split_slab_thread<D>(L, m / M + 1, t, j, k)) return false;
     s = (colour - j - k) % M;
     if (s < 0) s += M;
     const int i = M * t + s;
@@ -455,42 +539,18 @@ __device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colo
     return true;
 }
 
-// thread g of an all-interior pass -> interior vertex (run s)
+// all-interior pass: interior vertex at row position r (run s)
 template <int D>
-__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t g, int& s, int64_t& v) {
+__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int& s, int64_t& v) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
-    const int r = (int)(g % L.Rp);
-    const int64_t row = g / L.Rp;
-    int j, k;
-    if (D == 3) {
-        j = 1 + (int)(row % m);
-        k = 1 + (int)(row / m);
-        if (k > m) return false;
-    } else {
-        j = 1 + (int)row;
-        k = 0;
-        if (j > m) return false;
-    }
+    int r, j, k;
+    if (!split_slab_thread<D>(L, L.Rp, r, j, k)) return false;
     s = r / L.q;
     const int i = M * (r - s * L.q) + s;
     if (i < 1 || i > m) return false;
     v = (int64_t)k * L.Pp + (int64_t)j * L.Rp + r;
     return true;
-}
-
-template <int D>
-inline int64_t split_colour_threads(int n) {
-    const int m = n - 1;
-    if (m <= 0) return 0;
-    return (int64_t)(m / (D + 1) + 1) * m * (D == 3 ? m : 1);
-}
-
-template <int D>
-inline int64_t split_all_threads(const LevelView& L) {
-    const int m = L.n - 1;
-    if (m <= 0) return 0;
-    return (int64_t)L.Rp * m * (D == 3 ? m : 1);
 }
 
 template <int D, int NF, typename T, typename C>
@@ -508,21 +568,15 @@ template <int D, int NF, typename T, typename C>
 __device__ __forceinline__ void load_guarded_split(const LevelView& L, const T* __restrict__ xs,
                                                    const int (&ijk)[3], int f0,
                                                    C (&V)[NF][KuhnTables<D>::NB]) {
-    constexpr auto& TT = Kuhn<D>::T;
-    constexpr int NB = KuhnTables<D>::NB;
-#pragma unroll
-    for (int o = 0; o < NB; ++o) {
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int c = ijk[a] + TT.off[o][a];
-            in = in && (c >= 0) && (c <= L.n);
-        }
-        const int64_t e = in ? sidx<D>(L, ijk[0] + TT.off[o][0], ijk[1] + TT.off[o][1], ijk[2] + TT.off[o][2])
-                             : (int64_t)0;
+    static_for<0, KuhnTables<D>::NB>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
+        const bool in = (ijk[0] + dx >= 0) && (ijk[0] + dx <= L.n) && (ijk[1] + dy >= 0) &&
+                        (ijk[1] + dy <= L.n) && (D == 2 || ((ijk[2] + dz >= 0) && (ijk[2] + dz <= L.n)));
+        const int64_t e = in ? sidx<D>(L, ijk[0] + dx, ijk[1] + dy, ijk[2] + dz) : (int64_t)0;
 #pragma unroll
         for (int f = 0; f < NF; ++f) V[f][o] = in ? (C)xs[(int64_t)(f0 + f) * L.Ns + e] : (C)0;
-    }
+    });
 }
 
 // canonical (x fastest) <-> colour-split copies of nf fields.  The pack
@@ -579,30 +633,123 @@ __device__ __forceinline__ void block_gs_update(C (&r)[D], const C (&Dm)[D][D], 
     }
 }
 
+// All-interior right-hand-side passes.  A thread owns position t of every
+// run of a row, i.e. the d+1 consecutive vertices i = (d+1) t + s, so one
+// coalesced load per run fetches a footprint row for all of them; the x
+// neighbours outside the group (i - 1 of s = 0, i + 1 of s = d) come from
+// the neighbouring lanes, or from a direct load at row ends and wave edges.
+// The stencil weights are the compile-time integer stencils of the Kuhn
+// lattice (times -|T|/(d+1) for B and B^T, |T| for C).
+template <int D>
+__device__ __forceinline__ bool rhs_thread(const LevelView& L, int& t, int& j, int& k, int& tn) {
+    const int m = L.n - 1;
+    tn = m / (D + 1) + 1;                          // positions covering i = 1..m
+    const bool act = split_slab_thread<D>(L, tn, t, j, k);
+    if (!act) {                                    // keep the lane for the shuffles
+        j = m;
+        k = (D == 3) ? m : 0;
+    }
+    return act;
+}
+
+// v[0] = value at i = (d+1) t - 1, v[1 + s] = run s at t, v[d + 2] = value at
+// i = (d+1)(t + 1), for the row starting at split index rb of field f.
+// element e of field f through a 32-bit byte offset from the field base (a
+// field has far fewer than 2^29 entries), so the loads use a scalar base
+// and one 32-bit offset register
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ f, uint32_t e) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(f) + e * (uint32_t)sizeof(T));
+}
+
+template <int D, typename T, typename C>
+__device__ __forceinline__ void row_runs(const LevelView& L, const T* __restrict__ f, uint32_t rb, int t,
+                                         int tn, C (&v)[D + 3]) {
+    constexpr int M = D + 1;
+    const uint32_t q = (uint32_t)L.q;
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[1 + r] = (C)ld32(f, rb + (uint32_t)r * q + (uint32_t)t);
+    // the two outer neighbours lie in the same cache lines as the runs
+    // (shifted by one position), so direct loads cost little
+    // (clamped addresses and selects instead of branches)
+    const C lv = (C)ld32(f, rb + (uint32_t)(M - 1) * q + (uint32_t)(t > 0 ? t - 1 : 0));
+    const C rv = (C)ld32(f, rb + (uint32_t)min(t + 1, L.q - 1));
+    v[0] = (t > 0) ? lv : (C)0;
+    v[M + 1] = (M * (t + 1) <= L.n) ? rv : (C)0;
+    (void)tn;
+}
+
+constexpr int ROW_DY[7] = {0, 1, -1, 0, 0, 1, -1};
+constexpr int ROW_DZ[7] = {0, 0, 0, 1, -1, 1, -1};
+template <int D> constexpr int rhs_rows() { return D == 3 ? 7 : 3; }
+
+// does footprint row (dy, dz) carry a nonzero weight?  KIND 0: B row of
+// component c; 1: B^T (any component); 2: C
+template <int D, int KIND, int CMP>
+constexpr bool row_used(int dy, int dz) {
+    for (int dx = -1; dx <= 1; ++dx) {
+        const int o = off_index<D>(dx, dy, dz);
+        if (o < 0) continue;
+        if (KIND == 0 && sdiv_int<D>(CMP, o) != 0) return true;
+        if (KIND == 2 && sc_int<D>(o) != 0) return true;
+        if (KIND == 1)
+            for (int l = 0; l < D; ++l)
+                if (sbt_int<D>(l, o) != 0) return true;
+    }
+    return false;
+}
+
 // g = f - B^T p on interior isoviscous vertices (p is fixed during the
 // velocity sweep, so the coupling term is formed once per sweep).
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restrict__ xs,
                                                    const T* __restrict__ bs, T* __restrict__ g) {
     using C = T;
-    constexpr int NB = KuhnTables<D>::NB;
-    int s;
-    int64_t v;
-    if (!split_all_vertex<D>(L, split_thread(), s, v)) return;
-    const XOff xo = x_offsets<D>(L, s);
-    const auto& E = ETab<D, C>::get();
-    const int ph = L.vphase_s[v];
-    C P[1][NB], bl[D];
-    load_split<D, 1, T, C>(L, xs, v, xo, D, P);
+    constexpr int M = D + 1;
+    int t, j, k, tn;
+    const bool act = rhs_thread<D>(L, t, j, k, tn);
+    const int64_t rb0 = (int64_t)k * L.Pp + (int64_t)j * L.Rp;
+    C acc[D][M];
 #pragma unroll
-    for (int l = 0; l < D; ++l) bl[l] = (C)bs[(int64_t)l * L.Ns + v];
-    if (ph == SPECIAL) return;
+    for (int l = 0; l < D; ++l)
 #pragma unroll
-    for (int l = 0; l < D; ++l) {
-        C acc = 0;
+        for (int q = 0; q < M; ++q) acc[l][q] = 0;
+    static_for<0, rhs_rows<D>()>([&](auto rc) {
+        constexpr int dy = ROW_DY[decltype(rc)::value];
+        constexpr int dz = D == 3 ? ROW_DZ[decltype(rc)::value] : 0;
+        constexpr bool used = row_used<D, 1, 0>(dy, dz);
+        if constexpr (used) {
+            C v[M + 2];
+            row_runs<D, T, C>(L, xs + (int64_t)D * L.Ns, (uint32_t)(rb0 + (int64_t)dy * L.Rp + (int64_t)dz * L.Pp), t,
+                              tn, v);
+            static_for<0, M>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                static_for<0, 3>([&](auto xc) {
+                    constexpr int dx = decltype(xc)::value - 1;
+                    constexpr int o = off_index<D>(dx, dy, dz);
+                    if constexpr (o >= 0) {
+                        static_for<0, D>([&](auto lc) {
+                            constexpr int l = decltype(lc)::value;
+                            constexpr int w = sbt_int<D>(l, o);
+                            if constexpr (w != 0) acc[l][q] += (C)w * v[1 + q + dx];
+                        });
+                    }
+                });
+            });
+        }
+    });
+    if (!act) return;
+    const int m = L.n - 1;
+    const C sbv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
 #pragma unroll
-        for (int o = 1; o < NB; ++o) acc += E.Sbt[l][o] * P[0][o];
-        g[(int64_t)l * L.Ns + v] = (T)(bl[l] - (C)L.sB * acc);
+    for (int q = 0; q < M; ++q) {
+        const int i = M * t + q;
+        if (i < 1 || i > m) continue;
+        const int64_t v = rb0 + (int64_t)q * L.q + t;
+        if (L.vphase_s[v] == SPECIAL) continue;
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+            g[(int64_t)l * L.Ns + v] = (T)((C)bs[(int64_t)l * L.Ns + v] - sbv * acc[l][q]);
     }
 }
 
@@ -613,7 +760,7 @@ __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
-    if (!split_colour_vertex<D>(L, colour, split_thread(), s, v)) return;
+    if (!split_colour_vertex<D>(L, colour, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     // every load is issued before the phase test (all addresses are
@@ -693,7 +840,9 @@ __global__ __launch_bounds__(256) void k_gs_vel_special_s(LevelView L, int colou
 
 // Pressure: s = B u - C p - g on interior isoviscous vertices (u and p are
 // fixed during the pressure sweep), then one forward colour sweep of
-// Gauss-Seidel on C delta = s from delta = 0.
+// Gauss-Seidel on C delta = s from delta = 0.  One vertex per thread: the
+// 15-point rows of four fields are too many live values for the grouped
+// form used by the velocity right-hand side.
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
                                                  const T* __restrict__ bs, T* __restrict__ sres) {
@@ -701,7 +850,7 @@ __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restric
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
-    if (!split_all_vertex<D>(L, split_thread(), s, v)) return;
+    if (!split_all_vertex<D>(L, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -728,7 +877,7 @@ __global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T
     using C = T;
     int s;
     int64_t v;
-    if (!split_colour_vertex<D>(L, colour, split_thread(), s, v)) return;
+    if (!split_colour_vertex<D>(L, colour, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -894,13 +1043,14 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restri
                                                           int64_t n, double* __restrict__ partial,
                                                           int with_self) {
     __shared__ double sh[MD_TILE][4];
-    const int i0 = blockIdx.y * MD_TILE;
+    const int i0 = blockIdx.x * MD_TILE;          // tile fastest: w is re-read from L2
+    const int nblk = gridDim.y, bid = blockIdx.y;
     const int kk = k + with_self;
     const int cnt = min(MD_TILE, kk - i0);
     double acc[MD_TILE];
 #pragma unroll
     for (int q = 0; q < MD_TILE; ++q) acc[q] = 0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) {
         const double we = w[e];
 #pragma unroll
         for (int q = 0; q < MD_TILE; ++q) {
@@ -921,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restri
     __syncthreads();
     if (threadIdx.x < cnt) {
         const int q = threadIdx.x;
-        partial[(int64_t)(i0 + q) * gridDim.x + blockIdx.x] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
+        partial[(int64_t)(i0 + q) * nblk + bid] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
     }
 }
 
@@ -934,14 +1084,17 @@ __global__ __launch_bounds__(256) void k_dots2_partial(const double* __restrict_
                                                        const double* __restrict__ b, int64_t n,
                                                        double* __restrict__ partial) {
     constexpr int NX = 3;
+    // the vector tile is the fastest block index, so the tiles that share an
+    // element range run together and re-read a and b from L2
     __shared__ double sh[2 * MD_TILE + NX][4];
-    const int i0 = blockIdx.y * MD_TILE;
+    const int i0 = blockIdx.x * MD_TILE;
+    const int nblk = gridDim.y, bid = blockIdx.y;
     const int cnt = max(0, min(MD_TILE, k - i0));
-    const bool extras = blockIdx.y == 0;
+    const bool extras = blockIdx.x == 0;
     double acc_a[MD_TILE], acc_b[MD_TILE], ex[NX] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < MD_TILE; ++q) { acc_a[q] = 0; acc_b[q] = 0; }
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) {
         const double ae = a[e], be = b[e];
 #pragma unroll
         for (int q = 0; q < MD_TILE; ++q) {
@@ -963,11 +1116,11 @@ __global__ __launch_bounds__(256) void k_dots2_partial(const double* __restrict_
     __syncthreads();
     const int t = threadIdx.x;
     const double tot = (t < 2 * MD_TILE + NX) ? sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3] : 0.0;
-    if (t < cnt) partial[(int64_t)(i0 + t) * gridDim.x + blockIdx.x] = tot;
+    if (t < cnt) partial[(int64_t)(i0 + t) * nblk + bid] = tot;
     else if (t >= MD_TILE && t < MD_TILE + cnt)
-        partial[(int64_t)(k + i0 + t - MD_TILE) * gridDim.x + blockIdx.x] = tot;
+        partial[(int64_t)(k + i0 + t - MD_TILE) * nblk + bid] = tot;
     else if (extras && t >= 2 * MD_TILE && t < 2 * MD_TILE + NX)
-        partial[(int64_t)(2 * k + t - 2 * MD_TILE) * gridDim.x + blockIdx.x] = tot;
+        partial[(int64_t)(2 * k + t - 2 * MD_TILE) * nblk + bid] = tot;
 }
 
 // out[f] = sum of the nblk partials of slot f (one block per slot)
@@ -1067,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_buoyancy_bulk(LevelView L, const uint8_
                                                        double rho, double vol, double* __restrict__ b) {
     constexpr int NS = KuhnTables<D>::NS;
     int i, j, k;
-    if (!interior_vertex<D>(L, 0, 1, blockIdx.x, i, j, k)) return;
+    if (!interior_vertex<D>(L, blockIdx.x, i, j, k)) return;
     const int64_t v = i + j * L.sy + k * L.sz;
     const int ph = L.vphase[v];
     if (ph == SPECIAL) return;
@@ -1116,7 +1269,7 @@ static inline int64_t special_blocks(int64_t ns) { return (ns + 255) / 256; }
 
 template <int D, int F, int BLK, int MODE, typename T>
 static hipError_t apply_t(const LevelView& L, const T* x, const T* b, T* y, hipStream_t s) {
-    const int64_t nb = interior_blocks<D>(L.n, 1);
+    const int64_t nb = interior_blocks<D>(L.n);
     if (nb > 0)
         hipLaunchKernelGGL((k_apply_bulk<D, F, BLK, MODE, T>), dim3((unsigned)nb), dim3(BX, BY), 0, s,
                            L, x, b, y);
@@ -1158,37 +1311,42 @@ static inline unsigned blocks256(int64_t threads) { return (unsigned)((threads +
 // 0..d-1 during the velocity sweep, s = B u - C p - g in field 0 and delta in
 // field d during the pressure sweep.
 template <int D, int F, typename T>
-static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs, T* ws, hipStream_t s) {
-    const int64_t ta = split_all_threads<D>(L);
-    const int64_t tc = split_colour_threads<D>(L.n);
+static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs, T* ws, hipStream_t s,
+                           PhaseTimer* tm) {
+    const int64_t ba = split_slab_blocks<D>(L.n, (L.n - 1) / (D + 1) + 1);   // grouped (velocity rhs)
+    const int64_t bp = split_slab_blocks<D>(L.n, L.Rp);                      // one vertex per thread
+    const int64_t bc = split_slab_blocks<D>(L.n, (L.n - 1) / (D + 1) + 1);
     T* g = ws;
     T* sres = ws;
     T* delta = ws + (int64_t)D * L.Ns;
-    if (ta > 0)
-        hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3(blocks256(ta)), dim3(256), 0, s, L, xs, bs, g);
+    if (ba > 0)
+        hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, g);
     for (int pass = 0; pass < 2; ++pass) {
         for (int cc = 0; cc <= D; ++cc) {
             const int c = pass == 0 ? cc : D - cc;
             const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
+            if (tm) (void)hipEventRecord(tm->begin[pass * (D + 1) + cc], s);
             if (pass == 0) {
-                if (tc > 0)
-                    hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3(blocks256(tc)), dim3(256), 0, s, L, c, xs, g);
+                if (bc > 0)
+                    hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
+                if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
                 if (ns > 0)
                     hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs);
             } else {
-                if (tc > 0)
-                    hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3(blocks256(tc)), dim3(256), 0, s, L, c, xs, g);
+                if (bc > 0)
+                    hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
+                if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
                 if (ns > 0)
                     hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs);
             }
         }
     }
     hipLaunchKernelGGL((k_fill_t<T>), grid1(L.Ns), dim3(256), 0, s, delta, L.Ns, (T)0);
-    if (ta > 0)
-        hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3(blocks256(ta)), dim3(256), 0, s, L, xs, bs, sres);
+    if (ba > 0)
+        hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3((unsigned)bp), dim3(256), 0, s, L, xs, bs, sres);
     for (int c = 0; c <= D; ++c) {
-        if (tc > 0)
-            hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3(blocks256(tc)), dim3(256), 0, s, L, c, sres, delta);
+        if (bc > 0)
+            hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, sres, delta);
         const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
         if (ns > 0)
             hipLaunchKernelGGL((k_gs_p_special_s<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
@@ -1200,21 +1358,21 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
 
 template <int D, typename T>
 static hipError_t smooth_d(const LevelView& L, int form, double omega, T* xs, const T* bs, T* ws,
-                           hipStream_t s) {
-    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, xs, bs, ws, s);
-    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, xs, bs, ws, s);
-    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, xs, bs, ws, s);
+                           hipStream_t s, PhaseTimer* tm) {
+    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, xs, bs, ws, s, tm);
+    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, xs, bs, ws, s, tm);
+    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, xs, bs, ws, s, tm);
     return hipErrorInvalidValue;
 }
 
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs, const void* bs,
-                         void* ws, hipStream_t s) {
+                         void* ws, hipStream_t s, PhaseTimer* tm) {
     if (prec == PREC_F64) {
-        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s);
-        return smooth_d<2, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s);
+        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s, tm);
+        return smooth_d<2, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s, tm);
     }
-    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s);
-    return smooth_d<2, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s);
+    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s, tm);
+    return smooth_d<2, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s, tm);
 }
 
 template <int D, typename T>
@@ -1299,7 +1457,7 @@ hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int6
     const int64_t cap = std::max<int64_t>(1, 65536 / std::max(1, kk));
     const int nblk = (int)std::min<int64_t>(std::min<int64_t>(1024, cap), std::max<int64_t>(1, (n + 255) / 256));
     const int tiles = (kk + MD_TILE - 1) / MD_TILE;
-    hipLaunchKernelGGL(k_multidot_partial, dim3(nblk, tiles), dim3(256), 0, s, V, ldv, k, w, n, partial, with_self);
+    hipLaunchKernelGGL(k_multidot_partial, dim3(tiles, nblk), dim3(256), 0, s, V, ldv, k, w, n, partial, with_self);
     hipLaunchKernelGGL(k_sum_slots, dim3(kk), dim3(256), 0, s, partial, nblk, out);
     return hipGetLastError();
 }
@@ -1310,7 +1468,7 @@ hipError_t k_dots2(const double* V, int64_t ldv, int k, const double* a, const d
     const int nblk = (int)std::min<int64_t>(std::min<int64_t>(1024, 65536 / slots),
                                             std::max<int64_t>(1, (n + 255) / 256));
     const int tiles = std::max(1, (k + MD_TILE - 1) / MD_TILE);
-    hipLaunchKernelGGL(k_dots2_partial, dim3(nblk, tiles), dim3(256), 0, s, V, ldv, k, a, b, n, partial);
+    hipLaunchKernelGGL(k_dots2_partial, dim3(tiles, nblk), dim3(256), 0, s, V, ldv, k, a, b, n, partial);
     hipLaunchKernelGGL(k_sum_slots, dim3(slots), dim3(256), 0, s, partial, nblk, out);
     return hipGetLastError();
 }
@@ -1358,7 +1516,7 @@ hipError_t k_dense_matvec(const double* A, int64_t m, const double* x, double* y
 hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* flag, double rho, double vol, double* b,
                           hipStream_t s) {
     const int D = L.dim;
-    const int64_t nb = D == 3 ? interior_blocks<3>(L.n, 1) : interior_blocks<2>(L.n, 1);
+    const int64_t nb = D == 3 ? interior_blocks<3>(L.n) : interior_blocks<2>(L.n);
     const int64_t ns = L.spec_off[D + 1];
     if (D == 3) {
         if (nb > 0) hipLaunchKernelGGL(k_buoyancy_bulk<3>, dim3((unsigned)nb), dim3(BX, BY), 0, s, L, flag, rho, vol, b);
