@@ -503,11 +503,12 @@ __device__ __forceinline__ int64_t snb(const LevelView& L, const XOff& xo, int o
 // with run positions fastest, then rows, then planes.  `per_row` is the
 // number of positions per row the pass visits.  Returns false past the end.
 template <int D>
-__device__ __forceinline__ bool split_slab_thread(const LevelView& L, int per_row, int& pos, int& j, int& k) {
+__device__ __forceinline__ bool split_slab_thread(const LevelView& L, int64_t bid, int per_row, int& pos, int& j,
+                                                  int& k) {
     const int m = L.n - 1;
     const int rows = slab_rows(m);
-    const int xcd = (int)(blockIdx.x & (NXCD - 1));
-    const int64_t g = (int64_t)(blockIdx.x / NXCD) * 256 + threadIdx.x;
+    const int xcd = (int)(bid & (NXCD - 1));
+    const int64_t g = (bid / NXCD) * 256 + threadIdx.x;
     pos = (int)(g % per_row);
     const int64_t r = g / per_row;
     const int jl = (int)(r % rows);
@@ -526,11 +527,12 @@ inline int64_t split_slab_blocks(int n, int per_row) {
 
 // colour phase: interior vertex of colour `colour` (run s of its row)
 template <int D>
-__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int& s, int64_t& v) {
+__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int64_t bid, int& s,
+                                                    int64_t& v) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
     int t, j, k;
-    if (!split_slab_thread<D>(L, m / M + 1, t, j, k)) return false;
+    if (!split_slab_thread<D>(L, bid, m / M + 1, t, j, k)) return false;
     s = (colour - j - k) % M;
     if (s < 0) s += M;
     const int i = M * t + s;
@@ -541,11 +543,11 @@ __device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colo
 
 // all-interior pass: interior vertex at row position r (run s)
 template <int D>
-__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int& s, int64_t& v) {
+__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t bid, int& s, int64_t& v) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
     int r, j, k;
-    if (!split_slab_thread<D>(L, L.Rp, r, j, k)) return false;
+    if (!split_slab_thread<D>(L, bid, L.Rp, r, j, k)) return false;
     s = r / L.q;
     const int i = M * (r - s * L.q) + s;
     if (i < 1 || i > m) return false;
@@ -644,7 +646,7 @@ template <int D>
 __device__ __forceinline__ bool rhs_thread(const LevelView& L, int& t, int& j, int& k, int& tn) {
     const int m = L.n - 1;
     tn = m / (D + 1) + 1;                          // positions covering i = 1..m
-    const bool act = split_slab_thread<D>(L, tn, t, j, k);
+    const bool act = split_slab_thread<D>(L, blockIdx.x, tn, t, j, k);
     if (!act) {                                    // keep the lane for the shuffles
         j = m;
         k = (D == 3) ? m : 0;
@@ -754,13 +756,13 @@ __global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restr
 }
 
 template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
-                                                  const T* __restrict__ g) {
+__device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int64_t bid, T* __restrict__ xs,
+                                            const T* __restrict__ g) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
-    if (!split_colour_vertex<D>(L, colour, s, v)) return;
+    if (!split_colour_vertex<D>(L, colour, bid, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     // every load is issued before the phase test (all addresses are
@@ -811,11 +813,11 @@ __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __
 }
 
 template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_special_s(LevelView L, int colour, T* __restrict__ xs,
-                                                          const T* __restrict__ bs) {
+__device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colour, int64_t bid,
+                                                    T* __restrict__ xs, const T* __restrict__ bs) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t sp = L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t sp = L.spec_off[colour] + bid * 256 + threadIdx.x;
     if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
     vertex_ijk<D>(L, L.spec[sp], ijk);
@@ -850,7 +852,7 @@ __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restric
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
-    if (!split_all_vertex<D>(L, s, v)) return;
+    if (!split_all_vertex<D>(L, blockIdx.x, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -872,12 +874,12 @@ __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restric
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T* __restrict__ sres,
-                                                T* __restrict__ delta) {
+__device__ __forceinline__ void gs_p_body(const LevelView& L, int colour, int64_t bid, const T* __restrict__ sres,
+                                          T* __restrict__ delta) {
     using C = T;
     int s;
     int64_t v;
-    if (!split_colour_vertex<D>(L, colour, s, v)) return;
+    if (!split_colour_vertex<D>(L, colour, bid, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -894,11 +896,12 @@ __global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_special_s(LevelView L, int colour, const T* __restrict__ xs,
-                                                        const T* __restrict__ bs, T* __restrict__ delta) {
+__device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t bid,
+                                                  const T* __restrict__ xs, const T* __restrict__ bs,
+                                                  T* __restrict__ delta) {
     using C = T;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t sp = L.spec_off[colour] + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t sp = L.spec_off[colour] + bid * 256 + threadIdx.x;
     if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
     vertex_ijk<D>(L, L.spec[sp], ijk);
@@ -911,6 +914,49 @@ __global__ __launch_bounds__(256) void k_gs_p_special_s(LevelView L, int colour,
     element_rows<D, FORM_GRADIENT, false, true, true, true, C>(L, sp, U, P[0], Dl[0], r);
     const C sres = (C)L.sB * r.bdiv - (C)L.sC * r.cp - (C)bs[(int64_t)D * L.Ns + v];
     delta[v] = (T)((sres - (C)L.sC * r.cd) / ((C)L.sC * r.cjj));
+}
+
+// One colour phase, three launch shapes: bulk only, special only, and both
+// in one grid (bulk workgroups first) for small levels, where the launch
+// latency of two kernels costs more than the lower occupancy of the merged one.
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
+                                                  const T* __restrict__ g) {
+    gs_vel_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, g);
+}
+
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_special_s(LevelView L, int colour, T* __restrict__ xs,
+                                                          const T* __restrict__ bs) {
+    gs_vel_special_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, bs);
+}
+
+template <int D, int F, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_gs_vel_m(LevelView L, int colour, T* __restrict__ xs,
+                                                  const T* __restrict__ g, const T* __restrict__ bs,
+                                                  int64_t nbulk) {
+    if ((int64_t)blockIdx.x < nbulk) gs_vel_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, g);
+    else gs_vel_special_body<D, F, BWD, T>(L, colour, (int64_t)blockIdx.x - nbulk, xs, bs);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T* __restrict__ sres,
+                                                T* __restrict__ delta) {
+    gs_p_body<D, T>(L, colour, blockIdx.x, sres, delta);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_special_s(LevelView L, int colour, const T* __restrict__ xs,
+                                                        const T* __restrict__ bs, T* __restrict__ delta) {
+    gs_p_special_body<D, T>(L, colour, blockIdx.x, xs, bs, delta);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gs_p_m(LevelView L, int colour, const T* __restrict__ sres,
+                                                const T* __restrict__ xs, const T* __restrict__ bs,
+                                                T* __restrict__ delta, int64_t nbulk) {
+    if ((int64_t)blockIdx.x < nbulk) gs_p_body<D, T>(L, colour, blockIdx.x, sres, delta);
+    else gs_p_special_body<D, T>(L, colour, (int64_t)blockIdx.x - nbulk, xs, bs, delta);
 }
 
 template <typename T>
@@ -1304,6 +1350,9 @@ hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, 
 
 static inline unsigned blocks256(int64_t threads) { return (unsigned)((threads + 255) / 256); }
 
+// levels up to this size run each colour phase as one merged launch
+constexpr int MERGE_MAX_N = 64;
+
 // One Uzawa step (eq. Uzawa_smooth) on split-layout vectors: symmetric
 // velocity sweep (forward colours 0..d, backward d..0; bulk then special
 // launch per colour), then delta = 0, pressure forward sweep on C,
@@ -1319,6 +1368,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
     T* g = ws;
     T* sres = ws;
     T* delta = ws + (int64_t)D * L.Ns;
+    const bool merge = L.n <= MERGE_MAX_N;       // one launch per colour phase
     if (ba > 0)
         hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, g);
     for (int pass = 0; pass < 2; ++pass) {
@@ -1326,7 +1376,13 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             const int c = pass == 0 ? cc : D - cc;
             const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
             if (tm) (void)hipEventRecord(tm->begin[pass * (D + 1) + cc], s);
-            if (pass == 0) {
+            if (merge && bc > 0 && ns > 0) {
+                if (pass == 0)
+                    hipLaunchKernelGGL((k_gs_vel_m<D, F, false, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, xs, g, bs, bc);
+                else
+                    hipLaunchKernelGGL((k_gs_vel_m<D, F, true, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, xs, g, bs, bc);
+                if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
+            } else if (pass == 0) {
                 if (bc > 0)
                     hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
                 if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
@@ -1345,9 +1401,13 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
     if (ba > 0)
         hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3((unsigned)bp), dim3(256), 0, s, L, xs, bs, sres);
     for (int c = 0; c <= D; ++c) {
+        const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
+        if (merge && bc > 0 && ns > 0) {
+            hipLaunchKernelGGL((k_gs_p_m<D, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, sres, xs, bs, delta, bc);
+            continue;
+        }
         if (bc > 0)
             hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, sres, delta);
-        const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
         if (ns > 0)
             hipLaunchKernelGGL((k_gs_p_special_s<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
     }
