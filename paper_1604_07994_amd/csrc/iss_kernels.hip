@@ -152,20 +152,25 @@ __device__ __forceinline__ void load_guarded(const LevelView& L, const T* __rest
         constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
         const bool in = (ijk[0] + dx >= 0) && (ijk[0] + dx <= L.n) && (ijk[1] + dy >= 0) &&
                         (ijk[1] + dy <= L.n) && (D == 2 || ((ijk[2] + dz >= 0) && (ijk[2] + dz <= L.n)));
-        const int64_t nv = v + dx + (int64_t)dy * L.sy + (int64_t)dz * L.sz;
+        // unconditional load from a clamped index, then a select: no branch
+        const int64_t nv = in ? v + dx + (int64_t)dy * L.sy + (int64_t)dz * L.sz : v;
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
-            V[f][o] = in ? (C)x[(int64_t)(f0 + f) * L.N + nv] : (C)0;
+        for (int f = 0; f < NF; ++f) {
+            const C val = (C)x[(int64_t)(f0 + f) * L.N + nv];
+            V[f][o] = in ? val : (C)0;
+        }
     });
 }
 
+// (a lattice has fewer than 2^32 vertices: 32-bit division suffices)
 template <int D>
 __device__ __forceinline__ void vertex_ijk(const LevelView& L, int64_t v, int (&ijk)[3]) {
-    const int64_t n1 = L.n + 1;
-    ijk[0] = (int)(v % n1);
-    const int64_t r = v / n1;
-    ijk[1] = (int)(r % n1);
-    ijk[2] = (D == 3) ? (int)(r / n1) : 0;
+    const uint32_t n1 = (uint32_t)L.n + 1u, u = (uint32_t)v;
+    const uint32_t r = u / n1;
+    ijk[0] = (int)(u - r * n1);
+    const uint32_t r2 = r / n1;
+    ijk[1] = (int)(r - r2 * n1);
+    ijk[2] = (D == 3) ? (int)r2 : 0;
 }
 
 template <int D>
@@ -575,9 +580,13 @@ __device__ __forceinline__ void load_guarded_split(const LevelView& L, const T* 
         constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
         const bool in = (ijk[0] + dx >= 0) && (ijk[0] + dx <= L.n) && (ijk[1] + dy >= 0) &&
                         (ijk[1] + dy <= L.n) && (D == 2 || ((ijk[2] + dz >= 0) && (ijk[2] + dz <= L.n)));
+        // unconditional load from a clamped index, then a select: no branch
         const int64_t e = in ? sidx<D>(L, ijk[0] + dx, ijk[1] + dy, ijk[2] + dz) : (int64_t)0;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) V[f][o] = in ? (C)xs[(int64_t)(f0 + f) * L.Ns + e] : (C)0;
+        for (int f = 0; f < NF; ++f) {
+            const C val = (C)xs[(int64_t)(f0 + f) * L.Ns + e];
+            V[f][o] = in ? val : (C)0;
+        }
     });
 }
 
