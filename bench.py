@@ -211,18 +211,35 @@ def main():
         results[form] = {"seconds": sorted(times)[len(times) // 2], "all": times,
                          "iterations": info["iterations"], "relres": info["relres"],
                          "status": info["status"]}
+        if form == forms[0]:
+            x64 = x.clone()                  # FP64 solution of the main form
+    def field_errors(xm):
+        """relative L2 difference per field to the FP64 solve (pressure means
+        removed: the constant pressure is the null space of K)"""
+        out = []
+        for f in range(w["dim"] + 1):
+            a, c = xm[f * N:(f + 1) * N], x64[f * N:(f + 1) * N]
+            if f == w["dim"]:
+                a, c = a - a.mean(), c - c.mean()
+            out.append(float(torch.linalg.norm(a - c) / torch.linalg.norm(c)))
+        return out
+
     fp32 = None
     if not args.no_fp32:
-        x.zero_()
-        P.solve(forms[0], x, b, prec="fp32", rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
-        x.zero_()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        info = P.solve(forms[0], x, b, prec="fp32", rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
-        torch.cuda.synchronize()
-        fp32 = {"seconds": time.perf_counter() - t, "iterations": info["iterations"],
-                "relres": info["relres"], "status": info["status"]}
-        log("fp32-preconditioned %s: its %d relres %.2e %.3f s" % (forms[0], info["iterations"], info["relres"], fp32["seconds"]))
+        fp32 = {}
+        for prec in ("fp32", "bf16"):
+            x.zero_()
+            P.solve(forms[0], x, b, prec=prec, rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = P.solve(forms[0], x, b, prec=prec, rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+            torch.cuda.synchronize()
+            fp32[prec] = {"seconds": time.perf_counter() - t, "iterations": info["iterations"],
+                          "relres": info["relres"], "status": info["status"],
+                          "rel_error_per_field_vs_fp64": field_errors(x)}
+            log("%s-preconditioned %s: its %d relres %.2e %.3f s" % (prec, forms[0], info["iterations"],
+                                                                     info["relres"], fp32[prec]["seconds"]))
 
     learned = None
     if not args.no_learned:
@@ -289,7 +306,7 @@ def main():
         "forms": results,
         "strain_over_interface": (results["strain"]["seconds"] / results["interface"]["seconds"])
         if "strain" in results and "interface" in results else None,
-        "fp32_preconditioner": fp32,
+        "mixed_precision": fp32,
         "learned_correction": learned,
         "apply": apply_gbs,
         "smooth_step_ms": smooth_ms,

@@ -24,7 +24,8 @@
  * (d+1) N elements in total.  Velocity entries of boundary vertices are
  * Dirichlet values: inputs must hold 0 there and outputs hold 0 there.
  * Pressure lives on every vertex.  Element type: double for ISS_FP64,
- * float for ISS_FP32 (see each call).
+ * float for ISS_FP32, bfloat16 (1-8-7 bits, round to nearest even) for
+ * ISS_FP32_BF16STORE, whose arithmetic is FP32 (see each call).
  *
  * Memory ownership.  Vector arguments are device pointers owned by the
  * caller (any allocator; 8-byte aligned).  The library allocates and owns
@@ -65,7 +66,7 @@ enum iss_status {
 
 enum iss_form { ISS_GRADIENT = 0, ISS_STRAIN = 1, ISS_INTERFACE = 2 };
 enum iss_block { ISS_VELOCITY_ONLY = 0, ISS_FULL_STOKES = 1 };
-enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1 };
+enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1, ISS_FP32_BF16STORE = 2 };
 enum iss_outer { ISS_OUTER_RICHARDSON = 0, ISS_OUTER_FGMRES = 1 };
 enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1 };
 enum iss_coarse_mu { ISS_COARSE_MU_CENTROID = 0, ISS_COARSE_MU_AVERAGE = 1 };
@@ -201,7 +202,8 @@ int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b,
  * with one V-cycle as preconditioner.  prec = ISS_FP32 runs the V-cycle
  * (stencil applies, smoothers, transfers) in FP32 while the outer
  * residual, orthogonalisation, solution update and the coarsest solve
- * stay FP64.  info may be NULL. */
+ * stay FP64; ISS_FP32_BF16STORE does the same with the V-cycle's vectors
+ * stored in BF16.  info may be NULL. */
 int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
               const double* b, iss_solve_info* info, iss_stream_t stream);
 

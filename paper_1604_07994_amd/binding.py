@@ -17,6 +17,7 @@ BLOCKS = {"velocity": 0, "full": 1}
 OUTER = {"richardson": 0, "fgmres": 1}
 COARSE_MU = {"centroid": 0, "average": 1}
 PREC_F64, PREC_F32 = 0, 1
+PREC_BF16 = 2            # vectors stored in BF16, arithmetic in FP32
 
 _lib = None
 
@@ -118,7 +119,9 @@ def _prec(t):
         return PREC_F64
     if t.dtype == torch.float32:
         return PREC_F32
-    raise ValueError("vectors must be float64 or float32")
+    if t.dtype == torch.bfloat16:
+        return PREC_BF16
+    raise ValueError("vectors must be float64, float32 or bfloat16")
 
 
 def inclusions_to_c(inclusions):
@@ -262,7 +265,7 @@ class Problem:
         import torch
         hist = (ctypes.c_double * (maxit + 1))()
         info = SolveInfo(0, 0.0, 0.0, 0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), 0, 0)
-        rc = lib().iss_solve(self._h, FORMS[form], PREC_F64 if prec == "fp64" else PREC_F32, rtol,
+        rc = lib().iss_solve(self._h, FORMS[form], {"fp64": PREC_F64, "fp32": PREC_F32, "bf16": PREC_BF16}[prec], rtol,
                              maxit, self._vec(x, self.levels, torch.float64),
                              self._vec(b, self.levels, torch.float64), ctypes.byref(info), _stream())
         if rc != 0 and raise_on_fail:

@@ -185,10 +185,10 @@ struct Level {
     float* d_mu32 = nullptr;
     float* d_imu32 = nullptr;
     int64_t ninterface = 0, nboundary = 0;
-    void* w_x[2] = {nullptr, nullptr};
-    void* w_b[2] = {nullptr, nullptr};
-    void* w_r[2] = {nullptr, nullptr};
-    void* w_s[2] = {nullptr, nullptr};      // split layout: xs, bs, ws (d+1 fields each)
+    void* w_x[3] = {nullptr, nullptr, nullptr};
+    void* w_b[3] = {nullptr, nullptr, nullptr};
+    void* w_r[3] = {nullptr, nullptr, nullptr};
+    void* w_s[3] = {nullptr, nullptr, nullptr};   // split layout: xs, bs, ws (d+1 fields each)
 };
 
 struct Coarse {
@@ -558,12 +558,12 @@ int setup_level(iss_problem* p, int l) {
 int ensure_work(iss_problem* p, int l, int prec) {
     Level& L = p->lv[l];
     if (L.w_x[prec]) return ISS_OK;
-    const size_t bytes = (size_t)(p->dim + 1) * L.v.N * (prec == PREC_F64 ? 8 : 4);
+    const size_t bytes = (size_t)(p->dim + 1) * L.v.N * prec_bytes(prec);
     int rc;
     if ((rc = dev_alloc(p, &L.w_x[prec], bytes))) return rc;
     if ((rc = dev_alloc(p, &L.w_b[prec], bytes))) return rc;
     if ((rc = dev_alloc(p, &L.w_r[prec], bytes))) return rc;
-    const size_t sbytes = (size_t)3 * (p->dim + 1) * L.v.Ns * (prec == PREC_F64 ? 8 : 4);
+    const size_t sbytes = (size_t)3 * (p->dim + 1) * L.v.Ns * prec_bytes(prec);
     if ((rc = dev_alloc(p, &L.w_s[prec], sbytes))) return rc;
     return ISS_OK;
 }
@@ -571,7 +571,7 @@ int ensure_work(iss_problem* p, int l, int prec) {
 // split-layout buffers of a level: xs, bs, ws (d+1 fields of Ns each)
 void split_buffers(iss_problem* p, int l, int prec, void** xs, void** bs, void** ws) {
     const Level& L = p->lv[l];
-    const size_t vec = (size_t)(p->dim + 1) * L.v.Ns * (prec == PREC_F64 ? 8 : 4);
+    const size_t vec = (size_t)(p->dim + 1) * L.v.Ns * prec_bytes(prec);
     char* base = (char*)L.w_s[prec];
     *xs = base;
     *bs = base + vec;
@@ -730,7 +730,7 @@ int ensure_coarse(iss_problem* p, int form) {
 // multigrid
 
 int check_form(int form) { return (form >= 0 && form <= 2) ? ISS_OK : fail(ISS_E_INVAL, "bad form"); }
-int check_prec(int prec) { return (prec == 0 || prec == 1) ? ISS_OK : fail(ISS_E_INVAL, "bad precision"); }
+int check_prec(int prec) { return (prec >= 0 && prec <= 2) ? ISS_OK : fail(ISS_E_INVAL, "bad precision"); }
 int check_level(const iss_problem* p, int l) {
     return (l >= p->coarse && l <= p->levels) ? ISS_OK : fail(ISS_E_INVAL, "level out of range");
 }
@@ -806,9 +806,11 @@ int precondition(iss_problem* p, int form, int prec, const double* v, double* z,
     if (prec == PREC_F64) {
         if ((rc = vcycle(p, l, form, PREC_F64, z, v, true, s))) return rc;
     } else {
-        ISS_HIP(k_convert(PREC_F64, v, PREC_F32, L.w_b[PREC_F32], n, s));
-        if ((rc = vcycle(p, l, form, PREC_F32, L.w_x[PREC_F32], L.w_b[PREC_F32], true, s))) return rc;
-        ISS_HIP(k_convert(PREC_F32, L.w_x[PREC_F32], PREC_F64, z, n, s));
+        // FP32 arithmetic, vectors stored in FP32 or BF16 (same exponent
+        // range as FP64 needs here, so no scaling)
+        ISS_HIP(k_convert(PREC_F64, v, prec, L.w_b[prec], n, s));
+        if ((rc = vcycle(p, l, form, prec, L.w_x[prec], L.w_b[prec], true, s))) return rc;
+        ISS_HIP(k_convert(prec, L.w_x[prec], PREC_F64, z, n, s));
     }
     if (p->net) {
         // band correction of the V-cycle output from the residual it leaves,

@@ -17,7 +17,8 @@ constexpr uint8_t OUTSIDE = 255;   // incident-element phase: outside the domain
 enum { FORM_GRADIENT = 0, FORM_STRAIN = 1, FORM_INTERFACE = 2 };
 enum { BLOCK_VEL = 0, BLOCK_FULL = 1 };
 enum { MODE_APPLY = 0, MODE_RESID = 1 };
-enum { PREC_F64 = 0, PREC_F32 = 1 };
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };   // storage; BF16 is computed in FP32
+inline int prec_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
 
 // Per-level data as seen by the kernels (all pointers are device pointers).
 struct LevelView {

@@ -33,6 +33,10 @@ template <> struct ETab<3, float> { __device__ static const ElemTables<3, float>
 template <> struct ETab<2, double> { __device__ static const ElemTables<2, double>& get() { return g_e2d; } };
 template <> struct ETab<2, float> { __device__ static const ElemTables<2, float>& get() { return g_e2f; } };
 
+// Arithmetic type of a storage type: BF16-stored vectors are computed in FP32.
+template <typename T> struct Acc { using type = T; };
+template <> struct Acc<__bf16> { using type = float; };
+
 template <typename T> struct Prec;
 template <> struct Prec<double> {
     __device__ static double mu(const LevelView& L, int ph) { return L.mu64[ph]; }
@@ -314,7 +318,7 @@ __device__ __forceinline__ void element_rows(const LevelView& L, int64_t s,
 template <int D, int F, int BLK, int MODE, typename T>
 __device__ __forceinline__ void apply_bulk_body(const LevelView& L, int64_t bid, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     int i, j, k;
     if (!interior_vertex<D>(L, bid, i, j, k)) return;
@@ -386,7 +390,7 @@ __device__ __forceinline__ void apply_bulk_body(const LevelView& L, int64_t bid,
     for (int f = 0; f <= D; ++f) {
         const int64_t e = (int64_t)f * L.N + v;
         if (MODE == MODE_RESID)
-            y[e] = (BLK == BLOCK_FULL || f < D) ? (T)(b[e] - out[f]) : (T)0;
+            y[e] = (BLK == BLOCK_FULL || f < D) ? (T)((C)b[e] - out[f]) : (T)0.0f;
         else
             y[e] = (T)out[f];
     }
@@ -395,7 +399,7 @@ __device__ __forceinline__ void apply_bulk_body(const LevelView& L, int64_t bid,
 template <int D, int F, int BLK, int MODE, typename T>
 __device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ y) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     if (s >= L.spec_off[D + 1]) return;
     const int64_t v = L.spec[s];
@@ -421,7 +425,7 @@ __device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s
         for (int f = 0; f <= D; ++f) {
             const int64_t e = (int64_t)f * L.N + v;
             if (MODE == MODE_RESID)
-                y[e] = (f == D && BLK == BLOCK_FULL) ? (T)(b[e] - out[f]) : (T)0;
+                y[e] = (f == D && BLK == BLOCK_FULL) ? (T)((C)b[e] - out[f]) : (T)0.0f;
             else
                 y[e] = (T)out[f];
         }
@@ -442,7 +446,7 @@ __device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s
         const int64_t e = (int64_t)f * L.N + v;
         if (MODE == MODE_RESID) {
             const bool zero = (f < D && bnd) || (f == D && BLK != BLOCK_FULL);
-            y[e] = zero ? (T)0 : (T)(b[e] - out[f]);
+            y[e] = zero ? (T)0.0f : (T)((C)b[e] - out[f]);
         } else {
             y[e] = (T)out[f];
         }
@@ -605,7 +609,7 @@ __global__ __launch_bounds__(256) void k_pack_t(LevelView L, const T* __restrict
     const int s = r / L.q;
     const int i = M * (r - s * L.q) + s;
     const int64_t n1 = L.n + 1;
-    out[(int64_t)f * per + e] = (i <= L.n) ? in[(int64_t)f * L.N + row * n1 + i] : (T)0;
+    out[(int64_t)f * per + e] = (i <= L.n) ? in[(int64_t)f * L.N + row * n1 + i] : (T)0.0f;
 }
 
 template <int D, typename T>
@@ -715,7 +719,7 @@ constexpr bool row_used(int dy, int dz) {
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restrict__ xs,
                                                    const T* __restrict__ bs, T* __restrict__ g) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int M = D + 1;
     int t, j, k, tn;
     const bool act = rhs_thread<D>(L, t, j, k, tn);
@@ -767,7 +771,7 @@ __global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restr
 template <int D, int F, bool BWD, typename T>
 __device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int64_t bid, T* __restrict__ xs,
                                             const T* __restrict__ g) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
@@ -824,7 +828,7 @@ __device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int6
 template <int D, int F, bool BWD, typename T>
 __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colour, int64_t bid,
                                                     T* __restrict__ xs, const T* __restrict__ bs) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     const int64_t sp = L.spec_off[colour] + bid * 256 + threadIdx.x;
     if (sp >= L.spec_off[colour + 1]) return;
@@ -857,7 +861,7 @@ __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colo
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
                                                  const T* __restrict__ bs, T* __restrict__ sres) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
@@ -885,7 +889,7 @@ __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restric
 template <int D, typename T>
 __device__ __forceinline__ void gs_p_body(const LevelView& L, int colour, int64_t bid, const T* __restrict__ sres,
                                           T* __restrict__ delta) {
-    using C = T;
+    using C = typename Acc<T>::type;
     int s;
     int64_t v;
     if (!split_colour_vertex<D>(L, colour, bid, s, v)) return;
@@ -908,7 +912,7 @@ template <int D, typename T>
 __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t bid,
                                                   const T* __restrict__ xs, const T* __restrict__ bs,
                                                   T* __restrict__ delta) {
-    using C = T;
+    using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     const int64_t sp = L.spec_off[colour] + bid * 256 + threadIdx.x;
     if (sp >= L.spec_off[colour + 1]) return;
@@ -969,13 +973,14 @@ __global__ __launch_bounds__(256) void k_gs_p_m(LevelView L, int colour, const T
 }
 
 template <typename T>
-__global__ void k_axpy_field(T* __restrict__ p, const T* __restrict__ d, T w, int64_t n) {
+__global__ void k_axpy_field(T* __restrict__ p, const T* __restrict__ d, typename Acc<T>::type w, int64_t n) {
+    using C = typename Acc<T>::type;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) p[e] += w * d[e];
+    if (e < n) p[e] = (T)((C)p[e] + w * (C)d[e]);
 }
 
 template <typename T>
-__global__ void k_fill_t(T* __restrict__ x, int64_t n, T val) {
+__global__ void k_fill_t(T* __restrict__ x, int64_t n, typename Acc<T>::type val) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) x[e] = val;
 }
@@ -989,6 +994,7 @@ template <int D, typename T>
 __global__ __launch_bounds__(256) void k_restrict_t(LevelView Lf, LevelView Lc,
                                                     const T* __restrict__ rf,
                                                     T* __restrict__ rc) {
+    using C = typename Acc<T>::type;
     constexpr auto& TT = Kuhn<D>::T;
     constexpr int NB = KuhnTables<D>::NB;
     const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -997,9 +1003,9 @@ __global__ __launch_bounds__(256) void k_restrict_t(LevelView Lf, LevelView Lc,
     vertex_ijk<D>(Lc, I, c);
     const bool bnd = on_boundary<D>(Lc, c);
     const int64_t F = 2 * c[0] + 2 * c[1] * Lf.sy + 2 * c[2] * Lf.sz;
-    T acc[D + 1];
+    C acc[D + 1];
 #pragma unroll
-    for (int f = 0; f <= D; ++f) acc[f] = rf[(int64_t)f * Lf.N + F];
+    for (int f = 0; f <= D; ++f) acc[f] = (C)rf[(int64_t)f * Lf.N + F];
 #pragma unroll
     for (int o = 1; o < NB; ++o) {
         bool in = true;
@@ -1011,10 +1017,10 @@ __global__ __launch_bounds__(256) void k_restrict_t(LevelView Lf, LevelView Lc,
         if (!in) continue;
         const int64_t fo = F + nb_lin<D>(Lf, o);
 #pragma unroll
-        for (int f = 0; f <= D; ++f) acc[f] += (T)0.5 * rf[(int64_t)f * Lf.N + fo];
+        for (int f = 0; f <= D; ++f) acc[f] += (C)0.5 * (C)rf[(int64_t)f * Lf.N + fo];
     }
 #pragma unroll
-    for (int f = 0; f <= D; ++f) rc[(int64_t)f * Lc.N + I] = (f < D && bnd) ? (T)0 : acc[f];
+    for (int f = 0; f <= D; ++f) rc[(int64_t)f * Lc.N + I] = (f < D && bnd) ? (T)0.0f : (T)acc[f];
 }
 
 template <int D, typename T>
@@ -1039,8 +1045,10 @@ __global__ __launch_bounds__(256) void k_prolong_t(LevelView Lf, LevelView Lc,
 #pragma unroll
     for (int f = 0; f <= D; ++f) {
         const T* e = ec + (int64_t)f * Lc.N;
-        const T val = odd ? (T)0.5 * (e[cl] + e[ch]) : e[cl];
-        xf[(int64_t)f * Lf.N + v] += val;
+        using C = typename Acc<T>::type;
+        const C val = odd ? (C)0.5 * ((C)e[cl] + (C)e[ch]) : (C)e[cl];
+        T* dst = xf + (int64_t)f * Lf.N + v;
+        *dst = (T)((C)*dst + val);
     }
 }
 
@@ -1070,7 +1078,7 @@ __global__ __launch_bounds__(256) void k_sumsq_partial(const T* __restrict__ x, 
         double acc = 0;
         const T* xf = x + (int64_t)f * N;
         for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
-            const double t = (double)xf[e];
+            const double t = (double)(typename Acc<T>::type)xf[e];
             acc += t * t;
         }
         const double s = block_sum<256>(acc, sh);
@@ -1237,14 +1245,14 @@ template <typename Ti, typename To>
 __global__ __launch_bounds__(256) void k_convert_t(const Ti* __restrict__ in, To* __restrict__ out,
                                                    int64_t n) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < n) out[e] = (To)in[e];
+    if (e < n) out[e] = (To)(typename Acc<To>::type)(typename Acc<Ti>::type)in[e];
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_t(const T* __restrict__ x, const int32_t* __restrict__ idx,
                                                   int64_t m, double* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < m) out[e] = (double)x[idx[e]];
+    if (e < m) out[e] = (double)(typename Acc<T>::type)x[idx[e]];
 }
 
 template <typename T>
@@ -1252,7 +1260,7 @@ __global__ __launch_bounds__(256) void k_scatter_t(const double* __restrict__ in
                                                    const int32_t* __restrict__ idx, int64_t m,
                                                    T* __restrict__ x) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < m) x[idx[e]] = (T)in[e];
+    if (e < m) x[idx[e]] = (T)(typename Acc<T>::type)in[e];
 }
 
 // y = A x, A dense m x m row major; one wavefront per row.
@@ -1304,6 +1312,18 @@ __global__ __launch_bounds__(256) void k_buoyancy_special(LevelView L, const uin
 
 static inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
+// storage type T of a precision code, then the statements
+#define ISS_BY_PREC(prec, ...)                                \
+    switch (prec) {                                           \
+        case PREC_F64: { using T = double; __VA_ARGS__; }     \
+        break;                                                \
+        case PREC_F32: { using T = float; __VA_ARGS__; }      \
+        break;                                                \
+        case PREC_BF16: { using T = __bf16; __VA_ARGS__; }    \
+        break;                                                \
+        default: return hipErrorInvalidValue;                 \
+    }
+
 hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t32, size_t bytes32) {
     hipError_t e;
     if (dim == 3) {
@@ -1349,12 +1369,10 @@ static hipError_t apply_d(const LevelView& L, int form, int block, int mode, con
 
 hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, const void* x,
                    const void* b, void* y, hipStream_t s) {
-    if (prec == PREC_F64) {
-        if (L.dim == 3) return apply_d<3, double>(L, form, block, mode, (const double*)x, (const double*)b, (double*)y, s);
-        return apply_d<2, double>(L, form, block, mode, (const double*)x, (const double*)b, (double*)y, s);
-    }
-    if (L.dim == 3) return apply_d<3, float>(L, form, block, mode, (const float*)x, (const float*)b, (float*)y, s);
-    return apply_d<2, float>(L, form, block, mode, (const float*)x, (const float*)b, (float*)y, s);
+    ISS_BY_PREC(prec,
+        if (L.dim == 3) return apply_d<3, T>(L, form, block, mode, (const T*)x, (const T*)b, (T*)y, s);
+        return apply_d<2, T>(L, form, block, mode, (const T*)x, (const T*)b, (T*)y, s))
+    return hipErrorInvalidValue;
 }
 
 static inline unsigned blocks256(int64_t threads) { return (unsigned)((threads + 255) / 256); }
@@ -1406,7 +1424,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             }
         }
     }
-    hipLaunchKernelGGL((k_fill_t<T>), grid1(L.Ns), dim3(256), 0, s, delta, L.Ns, (T)0);
+    hipLaunchKernelGGL((k_fill_t<T>), grid1(L.Ns), dim3(256), 0, s, delta, L.Ns, (typename Acc<T>::type)0);
     if (ba > 0)
         hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3((unsigned)bp), dim3(256), 0, s, L, xs, bs, sres);
     for (int c = 0; c <= D; ++c) {
@@ -1421,7 +1439,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             hipLaunchKernelGGL((k_gs_p_special_s<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
     }
     hipLaunchKernelGGL((k_axpy_field<T>), grid1(L.Ns), dim3(256), 0, s, xs + (int64_t)D * L.Ns, delta,
-                       (T)omega, L.Ns);
+                       (typename Acc<T>::type)omega, L.Ns);
     return hipGetLastError();
 }
 
@@ -1436,12 +1454,10 @@ static hipError_t smooth_d(const LevelView& L, int form, double omega, T* xs, co
 
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs, const void* bs,
                          void* ws, hipStream_t s, PhaseTimer* tm) {
-    if (prec == PREC_F64) {
-        if (L.dim == 3) return smooth_d<3, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s, tm);
-        return smooth_d<2, double>(L, form, omega, (double*)xs, (const double*)bs, (double*)ws, s, tm);
-    }
-    if (L.dim == 3) return smooth_d<3, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s, tm);
-    return smooth_d<2, float>(L, form, omega, (float*)xs, (const float*)bs, (float*)ws, s, tm);
+    ISS_BY_PREC(prec,
+        if (L.dim == 3) return smooth_d<3, T>(L, form, omega, (T*)xs, (const T*)bs, (T*)ws, s, tm);
+        return smooth_d<2, T>(L, form, omega, (T*)xs, (const T*)bs, (T*)ws, s, tm))
+    return hipErrorInvalidValue;
 }
 
 template <int D, typename T>
@@ -1454,67 +1470,55 @@ static void split_t(const LevelView& L, int nf, const T* in, T* out, int dir, hi
 
 hipError_t k_split(const LevelView& L, int prec, int nf, const void* in, void* out, int dir, hipStream_t s) {
     if (nf <= 0) return hipSuccess;
-    if (prec == PREC_F64) {
-        if (L.dim == 3) split_t<3, double>(L, nf, (const double*)in, (double*)out, dir, s);
-        else split_t<2, double>(L, nf, (const double*)in, (double*)out, dir, s);
-    } else {
-        if (L.dim == 3) split_t<3, float>(L, nf, (const float*)in, (float*)out, dir, s);
-        else split_t<2, float>(L, nf, (const float*)in, (float*)out, dir, s);
-    }
+    ISS_BY_PREC(prec,
+        if (L.dim == 3) split_t<3, T>(L, nf, (const T*)in, (T*)out, dir, s);
+        else split_t<2, T>(L, nf, (const T*)in, (T*)out, dir, s))
     return hipGetLastError();
 }
 
 hipError_t k_restrict(const LevelView& Lf, const LevelView& Lc, int prec, const void* rf, void* rc,
                       hipStream_t s) {
-    if (prec == PREC_F64) {
-        if (Lf.dim == 3) hipLaunchKernelGGL((k_restrict_t<3, double>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const double*)rf, (double*)rc);
-        else hipLaunchKernelGGL((k_restrict_t<2, double>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const double*)rf, (double*)rc);
-    } else {
-        if (Lf.dim == 3) hipLaunchKernelGGL((k_restrict_t<3, float>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const float*)rf, (float*)rc);
-        else hipLaunchKernelGGL((k_restrict_t<2, float>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const float*)rf, (float*)rc);
-    }
+    ISS_BY_PREC(prec,
+        if (Lf.dim == 3) hipLaunchKernelGGL((k_restrict_t<3, T>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const T*)rf, (T*)rc);
+        else hipLaunchKernelGGL((k_restrict_t<2, T>), grid1(Lc.N), dim3(256), 0, s, Lf, Lc, (const T*)rf, (T*)rc))
     return hipGetLastError();
 }
 
 hipError_t k_prolong_add(const LevelView& Lf, const LevelView& Lc, int prec, const void* ec, void* xf,
                          hipStream_t s) {
-    if (prec == PREC_F64) {
-        if (Lf.dim == 3) hipLaunchKernelGGL((k_prolong_t<3, double>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const double*)ec, (double*)xf);
-        else hipLaunchKernelGGL((k_prolong_t<2, double>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const double*)ec, (double*)xf);
-    } else {
-        if (Lf.dim == 3) hipLaunchKernelGGL((k_prolong_t<3, float>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const float*)ec, (float*)xf);
-        else hipLaunchKernelGGL((k_prolong_t<2, float>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const float*)ec, (float*)xf);
-    }
+    ISS_BY_PREC(prec,
+        if (Lf.dim == 3) hipLaunchKernelGGL((k_prolong_t<3, T>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const T*)ec, (T*)xf);
+        else hipLaunchKernelGGL((k_prolong_t<2, T>), grid1(Lf.N), dim3(256), 0, s, Lf, Lc, (const T*)ec, (T*)xf))
     return hipGetLastError();
 }
 
 hipError_t k_fill(int prec, void* x, int64_t n, double value, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (prec == PREC_F64) hipLaunchKernelGGL((k_fill_t<double>), grid1(n), dim3(256), 0, s, (double*)x, n, value);
-    else hipLaunchKernelGGL((k_fill_t<float>), grid1(n), dim3(256), 0, s, (float*)x, n, (float)value);
+    ISS_BY_PREC(prec,
+        hipLaunchKernelGGL((k_fill_t<T>), grid1(n), dim3(256), 0, s, (T*)x, n, (typename Acc<T>::type)value))
     return hipGetLastError();
 }
 
 hipError_t k_convert(int prec_in, const void* in, int prec_out, void* out, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (prec_in == PREC_F64 && prec_out == PREC_F32)
-        hipLaunchKernelGGL((k_convert_t<double, float>), grid1(n), dim3(256), 0, s, (const double*)in, (float*)out, n);
-    else if (prec_in == PREC_F32 && prec_out == PREC_F64)
-        hipLaunchKernelGGL((k_convert_t<float, double>), grid1(n), dim3(256), 0, s, (const float*)in, (double*)out, n);
-    else if (prec_in == PREC_F64)
-        hipLaunchKernelGGL((k_convert_t<double, double>), grid1(n), dim3(256), 0, s, (const double*)in, (double*)out, n);
-    else
-        hipLaunchKernelGGL((k_convert_t<float, float>), grid1(n), dim3(256), 0, s, (const float*)in, (float*)out, n);
+    // one side is FP64 (the Krylov vectors), the other any storage type
+    if (prec_in == PREC_F64) {
+        ISS_BY_PREC(prec_out,
+            hipLaunchKernelGGL((k_convert_t<double, T>), grid1(n), dim3(256), 0, s, (const double*)in, (T*)out, n))
+    } else if (prec_out == PREC_F64) {
+        ISS_BY_PREC(prec_in,
+            hipLaunchKernelGGL((k_convert_t<T, double>), grid1(n), dim3(256), 0, s, (const T*)in, (double*)out, n))
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* partial, double* out,
                          hipStream_t s) {
     const int nblk = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (N + 255) / 256));
-    if (prec == PREC_F64)
-        hipLaunchKernelGGL((k_sumsq_partial<double>), dim3(nblk), dim3(256), 0, s, (const double*)x, N, nf, partial);
-    else
-        hipLaunchKernelGGL((k_sumsq_partial<float>), dim3(nblk), dim3(256), 0, s, (const float*)x, N, nf, partial);
+    ISS_BY_PREC(prec,
+        hipLaunchKernelGGL((k_sumsq_partial<T>), dim3(nblk), dim3(256), 0, s, (const T*)x, N, nf, partial))
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, nf, out);
     return hipGetLastError();
 }
@@ -1566,14 +1570,14 @@ hipError_t k_axpby(double* y, double a, const double* x, double b, int64_t n, hi
 }
 
 hipError_t k_gather(int prec, const void* x, const int32_t* idx, int64_t m, double* out, hipStream_t s) {
-    if (prec == PREC_F64) hipLaunchKernelGGL((k_gather_t<double>), grid1(m), dim3(256), 0, s, (const double*)x, idx, m, out);
-    else hipLaunchKernelGGL((k_gather_t<float>), grid1(m), dim3(256), 0, s, (const float*)x, idx, m, out);
+    ISS_BY_PREC(prec,
+        hipLaunchKernelGGL((k_gather_t<T>), grid1(m), dim3(256), 0, s, (const T*)x, idx, m, out))
     return hipGetLastError();
 }
 
 hipError_t k_scatter(int prec, const double* in, const int32_t* idx, int64_t m, void* x, hipStream_t s) {
-    if (prec == PREC_F64) hipLaunchKernelGGL((k_scatter_t<double>), grid1(m), dim3(256), 0, s, in, idx, m, (double*)x);
-    else hipLaunchKernelGGL((k_scatter_t<float>), grid1(m), dim3(256), 0, s, in, idx, m, (float*)x);
+    ISS_BY_PREC(prec,
+        hipLaunchKernelGGL((k_scatter_t<T>), grid1(m), dim3(256), 0, s, in, idx, m, (T*)x))
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ def to_dev(a, dtype=None):
 def to_host(t):
     import torch
     torch.cuda.synchronize()
-    return t.detach().cpu().numpy().astype(np.float64)
+    return t.detach().double().cpu().numpy()
 
 
 def small_workload(name, levels, macro=None, seed=0):

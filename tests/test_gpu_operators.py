@@ -80,6 +80,24 @@ def test_apply_fp32(case, form):
     assert_close_scaled(to_host(y), ref, abs_scale(K, x32), 2e-6, form)
 
 
+@pytest.mark.parametrize("form", ["strain", "interface"])
+def test_apply_bf16_storage(case, form):
+    """BF16-stored vectors, FP32 arithmetic: the input is the BF16 rounding
+    of x, the output is rounded to BF16 once (unit roundoff 2^-8)."""
+    import torch
+    w, P, D = case
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=13)
+    xb = to_dev(x, torch.bfloat16)
+    K = D.stokes(form)
+    xr = to_host(xb)
+    ref = K @ xr
+    y = torch.empty(x.size, dtype=torch.bfloat16, device="cuda")
+    P.apply(form, xb, y)
+    err = np.abs(to_host(y) - ref)
+    bound = 2.0 ** -8 * np.abs(ref) + 4e-6 * np.max(abs_scale(K, xr))
+    assert np.all(err <= bound), (form, float(np.max(err - bound)))
+
+
 @pytest.mark.parametrize("form", ["gradient", "strain", "interface"])
 def test_residual_and_norms(case, form):
     import torch
