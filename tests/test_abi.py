@@ -46,3 +46,55 @@ def test_argument_validation_without_gpu():
     opt = binding.Options()
     assert L.iss_default_options(ctypes.byref(opt)) == 0
     assert opt.nu1 == 3 and opt.nu2 == 3 and abs(opt.omega - 0.3) < 1e-15
+
+
+def _create(L, binding, dim=3, macro=1, levels=2, coarse=1, incs=(), mu=(1.0,), opt=None):
+    h = ctypes.c_void_p()
+    arr = binding.inclusions_to_c(list(incs))
+    m = (ctypes.c_double * max(1, len(mu)))(*mu)
+    rc = L.iss_problem_create(dim, macro, levels, coarse, arr, len(incs), m, len(mu),
+                              None if opt is None else ctypes.byref(opt), ctypes.byref(h))
+    return rc, L.iss_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(macro=0), "macro"),
+    (dict(levels=1, coarse=2), "coarse_level"),
+    (dict(coarse=0), "coarse_level"),
+    (dict(mu=()), "nphase"),
+    (dict(mu=tuple([1.0] * 255)), "nphase"),
+    (dict(mu=(1.0, float("inf"))), "viscosities"),
+    (dict(mu=(1.0, 0.0)), "viscosities"),
+    (dict(incs=[{"kind": "sphere", "center": (0.5, 0.5, 0.5), "radius": 0.2, "phase": 2}], mu=(1.0, 2.0)),
+     "phase"),
+    (dict(incs=[{"kind": "halfspace", "axis": 3, "threshold": 0.5, "phase": 1}], mu=(1.0, 2.0)), "axis"),
+])
+def test_problem_create_rejects_bad_arguments(kw, msg):
+    """Every argument check of iss_problem_create runs before any device
+    call: ISS_E_INVAL (-1) and a message naming the argument."""
+    from paper_1604_07994_amd import binding
+    L = binding.lib()
+    rc, err = _create(L, binding, **kw)
+    assert rc == -1 and msg in err, (rc, err)
+
+
+@pytest.mark.parametrize("field,value", [("nu1", -1), ("nu_inc", -2), ("restart", 0), ("outer", 5),
+                                         ("coarse_mu", 7), ("coarse_form", 3), ("stab_beta", 0.0)])
+def test_problem_create_rejects_bad_options(field, value):
+    from paper_1604_07994_amd import binding
+    L = binding.lib()
+    opt = binding.Options()
+    assert L.iss_default_options(ctypes.byref(opt)) == 0
+    setattr(opt, field, value)
+    rc, err = _create(L, binding, opt=opt)
+    assert rc == -1 and "options" in err, (rc, err)
+
+
+def test_null_arguments_are_rejected():
+    from paper_1604_07994_amd import binding
+    L = binding.lib()
+    assert L.iss_default_options(None) == -1
+    mu = (ctypes.c_double * 1)(1.0)
+    assert L.iss_problem_create(3, 1, 2, 1, None, 0, mu, 1, None, None) == -1
+    assert L.iss_apply(None, 2, 1, 2, 0, None, None, None) == -1
+    assert L.iss_solve(None, 2, 0, 1e-8, 10, None, None, None, None) == -1

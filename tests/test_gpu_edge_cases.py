@@ -116,3 +116,26 @@ def test_zero_input_gives_zero(case):
     y = torch.full_like(x, 7.0)
     P.apply("interface", x, y, block="full")
     assert torch.count_nonzero(y).item() == 0
+
+
+def test_call_errors_and_not_converged():
+    """Bad form, precision or level: ISS_E_INVAL and no device work; a solve
+    that hits maxit returns ISS_E_NOTCONV with its history filled."""
+    import ctypes
+    import torch
+    from paper_1604_07994_amd import binding
+    w = CASES["boundary-cut-3d"]
+    P = gpu_problem(w, outer="fgmres")
+    L = binding.lib()
+    x = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    xp, yp = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    assert L.iss_apply(P._h, 7, 1, w["levels"], 0, xp, yp, None) == -1
+    assert L.iss_apply(P._h, 2, 1, w["levels"], 9, xp, yp, None) == -1
+    assert L.iss_apply(P._h, 2, 1, w["levels"] + 1, 0, xp, yp, None) == -1
+    assert L.iss_apply(P._h, 2, 5, w["levels"], 0, xp, yp, None) == -1
+    b = to_dev(iss_inputs.random_rhs(3, w["n"], seed=45))
+    info = P.solve("interface", x, b, rtol=1e-14, maxit=2, raise_on_fail=False)
+    assert info["status"] == -3 and info["iterations"] == 2
+    assert len(info["history"]) == 3 and info["history"][-1] < info["history"][0]
+    P.close()
