@@ -12,7 +12,7 @@ rows) form in FP64: FGMRES(150) with one Uzawa V(5,5) cycle per iteration
 levels as in the paper's coarse-grid swap); the strain form is timed with the
 same solver.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -151,7 +151,7 @@ def learned_report(seeds=(100000, 100004)):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the library runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
