@@ -1101,6 +1101,7 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
 // V_i w, 16 vectors per workgroup row (blockIdx.y) so w is read once per
 // 16 dot products; vector k (i == k) is w itself when with_self is set.
 constexpr int MD_TILE = 16;
+constexpr int KRY_UNROLL = 8;   // basis vectors read per step of the combination kernels
 __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restrict__ V, int64_t ldv,
                                                           int k, const double* __restrict__ w,
                                                           int64_t n, double* __restrict__ partial,
@@ -1113,16 +1114,22 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restri
     double acc[MD_TILE];
 #pragma unroll
     for (int q = 0; q < MD_TILE; ++q) acc[q] = 0;
+    // rows past the tile's end re-read its last row (a cache hit) and are
+    // dropped by the select, so every load of an element is issued before
+    // the first wait
+    const double* rows[MD_TILE];
+#pragma unroll
+    for (int q = 0; q < MD_TILE; ++q) {
+        const int i = i0 + min(q, cnt - 1);
+        rows[q] = (i < k) ? V + (int64_t)i * ldv : w;
+    }
     for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) {
         const double we = w[e];
+        double vi[MD_TILE];
 #pragma unroll
-        for (int q = 0; q < MD_TILE; ++q) {
-            if (q < cnt) {
-                const int i = i0 + q;
-                const double vi = (i < k) ? V[(int64_t)i * ldv + e] : we;
-                acc[q] += vi * we;
-            }
-        }
+        for (int q = 0; q < MD_TILE; ++q) vi[q] = rows[q][e];
+#pragma unroll
+        for (int q = 0; q < MD_TILE; ++q) acc[q] += (q < cnt) ? vi[q] * we : 0.0;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -1138,10 +1145,67 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restri
     }
 }
 
+// EPT consecutive doubles per lane: EPT == 2 reads them with one 16-byte
+// load (the caller guarantees even n, even leading dimensions and 16-byte
+// aligned vectors)
+template <int EPT>
+__device__ __forceinline__ void ld_ept(const double* __restrict__ p, double (&o)[EPT]) {
+    if constexpr (EPT == 2) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 t = *reinterpret_cast<const d2*>(p);
+        o[0] = t.x;
+        o[1] = t.y;
+    } else {
+        o[0] = p[0];
+    }
+}
+template <int EPT>
+__device__ __forceinline__ void st_ept(double* __restrict__ p, const double (&o)[EPT]) {
+    if constexpr (EPT == 2) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        d2 t;
+        t.x = o[0];
+        t.y = o[1];
+        *reinterpret_cast<d2*>(p) = t;
+    } else {
+        p[0] = o[0];
+    }
+}
+
+// One element range of the dot pass for a tile of basis rows; FULL tiles
+// (cnt == MD_TILE) accumulate without the row mask.  All row loads of an
+// element are issued before the first wait.
+template <int EPT, bool FULL>
+__device__ __forceinline__ void dots2_range(const double* const (&rows)[MD_TILE], int cnt,
+                                            const double* __restrict__ a, const double* __restrict__ b,
+                                            int64_t n, int64_t e0, int64_t stride, bool extras,
+                                            double (&acc_a)[MD_TILE], double (&acc_b)[MD_TILE],
+                                            double (&ex)[3]) {
+    for (int64_t e = e0; e < n; e += stride) {
+        double ae[EPT], be[EPT], vi[MD_TILE][EPT];
+        ld_ept<EPT>(a + e, ae);
+        ld_ept<EPT>(b + e, be);
+#pragma unroll
+        for (int q = 0; q < MD_TILE; ++q) ld_ept<EPT>(rows[q] + e, vi[q]);
+#pragma unroll
+        for (int q = 0; q < MD_TILE; ++q) {
+            double sa = 0, sb = 0;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) { sa += vi[q][u] * ae[u]; sb += vi[q][u] * be[u]; }
+            if (FULL || q < cnt) { acc_a[q] += sa; acc_b[q] += sb; }
+        }
+        if (extras) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) { ex[0] += ae[u] * ae[u]; ex[1] += ae[u] * be[u]; ex[2] += be[u] * be[u]; }
+        }
+    }
+}
+
 // Gram-Schmidt with delayed reorthogonalisation: one pass computes, for a
 // tile of basis vectors V_i, the dot products V_i.a and V_i.b; tile 0 also
 // accumulates a.a, a.b and b.b.  Partial sums per block; slots [0, k) hold
 // V.a, [k, 2k) V.b, then a.a, a.b, b.b.
+template <int EPT>
 __global__ __launch_bounds__(256) void k_dots2_partial(const double* __restrict__ V, int64_t ldv, int k,
                                                        const double* __restrict__ a,
                                                        const double* __restrict__ b, int64_t n,
@@ -1157,18 +1221,15 @@ __global__ __launch_bounds__(256) void k_dots2_partial(const double* __restrict_
     double acc_a[MD_TILE], acc_b[MD_TILE], ex[NX] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < MD_TILE; ++q) { acc_a[q] = 0; acc_b[q] = 0; }
-    for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) {
-        const double ae = a[e], be = b[e];
+    // rows past the tile's end re-read its last row (a cache hit) and are
+    // masked; k == 0 reads a in place of a row
+    const double* rows[MD_TILE];
 #pragma unroll
-        for (int q = 0; q < MD_TILE; ++q) {
-            if (q < cnt) {
-                const double vi = V[(int64_t)(i0 + q) * ldv + e];
-                acc_a[q] += vi * ae;
-                acc_b[q] += vi * be;
-            }
-        }
-        if (extras) { ex[0] += ae * ae; ex[1] += ae * be; ex[2] += be * be; }
-    }
+    for (int q = 0; q < MD_TILE; ++q)
+        rows[q] = cnt > 0 ? V + (int64_t)(i0 + min(q, cnt - 1)) * ldv : a;
+    const int64_t e0 = ((int64_t)bid * 256 + threadIdx.x) * EPT, stride = (int64_t)nblk * 256 * EPT;
+    if (cnt == MD_TILE) dots2_range<EPT, true>(rows, cnt, a, b, n, e0, stride, extras, acc_a, acc_b, ex);
+    else dots2_range<EPT, false>(rows, cnt, a, b, n, e0, stride, extras, acc_a, acc_b, ex);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < 2 * MD_TILE + NX; ++q) {
@@ -1200,23 +1261,46 @@ __global__ __launch_bounds__(256) void k_sum_slots(const double* __restrict__ pa
 // Second pass of the delayed scheme: with c = V^T u and d = V^T w over the
 // k finished basis vectors (u = column k of V, the previous projected
 // vector), finish column k as v = (u - V c) / alpha and store the new
-// projected vector (w - V d - e v) / s in column k + 1.
+// projected vector (w - V d - e v) / s in column k + 1.  EPT elements per
+// lane; KRY_UNROLL rows in flight; the sums keep the order i = 0..k-1.
+template <int EPT>
 __global__ __launch_bounds__(256) void k_dcgs_update_t(double* __restrict__ V, int64_t ldv, int k,
                                                        const double* __restrict__ c,
                                                        const double* __restrict__ d,
                                                        const double* __restrict__ w, double inv_alpha,
                                                        double ecoef, double inv_s, int64_t n) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * EPT;
     if (e >= n) return;
-    double s1 = 0, s2 = 0;
-    for (int i = 0; i < k; ++i) {
-        const double vi = V[(int64_t)i * ldv + e];
-        s1 += c[i] * vi;
-        s2 += d[i] * vi;
+    double s1[EPT], s2[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) { s1[u] = 0; s2[u] = 0; }
+    int i = 0;
+    for (; i + KRY_UNROLL <= k; i += KRY_UNROLL) {
+        double vi[KRY_UNROLL][EPT];
+#pragma unroll
+        for (int r = 0; r < KRY_UNROLL; ++r) ld_ept<EPT>(V + (int64_t)(i + r) * ldv + e, vi[r]);
+#pragma unroll
+        for (int r = 0; r < KRY_UNROLL; ++r) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) { s1[u] += c[i + r] * vi[r][u]; s2[u] += d[i + r] * vi[r][u]; }
+        }
     }
-    const double v = (V[(int64_t)k * ldv + e] - s1) * inv_alpha;
-    V[(int64_t)k * ldv + e] = v;
-    V[(int64_t)(k + 1) * ldv + e] = (w[e] - s2 - ecoef * v) * inv_s;
+    for (; i < k; ++i) {
+        double vi[EPT];
+        ld_ept<EPT>(V + (int64_t)i * ldv + e, vi);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) { s1[u] += c[i] * vi[u]; s2[u] += d[i] * vi[u]; }
+    }
+    double uk[EPT], we[EPT], v[EPT], nx[EPT];
+    ld_ept<EPT>(V + (int64_t)k * ldv + e, uk);
+    ld_ept<EPT>(w + e, we);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        v[u] = (uk[u] - s1[u]) * inv_alpha;
+        nx[u] = (we[u] - s2[u] - ecoef * v[u]) * inv_s;
+    }
+    st_ept<EPT>(V + (int64_t)k * ldv + e, v);
+    st_ept<EPT>(V + (int64_t)(k + 1) * ldv + e, nx);
 }
 
 __global__ __launch_bounds__(256) void k_multiaxpy_t(double* __restrict__ y, const double* __restrict__ X,
@@ -1225,7 +1309,15 @@ __global__ __launch_bounds__(256) void k_multiaxpy_t(double* __restrict__ y, con
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     double acc = 0;
-    for (int i = 0; i < k; ++i) acc += c[i] * X[(int64_t)i * ldx + e];
+    int i = 0;
+    for (; i + KRY_UNROLL <= k; i += KRY_UNROLL) {
+        double xi[KRY_UNROLL];
+#pragma unroll
+        for (int u = 0; u < KRY_UNROLL; ++u) xi[u] = X[(int64_t)(i + u) * ldx + e];
+#pragma unroll
+        for (int u = 0; u < KRY_UNROLL; ++u) acc += c[i + u] * xi[u];
+    }
+    for (; i < k; ++i) acc += c[i] * X[(int64_t)i * ldx + e];
     y[e] += alpha * acc;
 }
 
@@ -1535,21 +1627,35 @@ hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int6
     return hipGetLastError();
 }
 
+// even length and leading dimension, 16-byte aligned vectors: the Krylov
+// kernels may read two doubles per lane
+static inline bool pair_aligned(int64_t n, int64_t ldv, const void* p, const void* q, const void* r) {
+    auto al = [](const void* x) { return ((uintptr_t)x & 15) == 0; };
+    return n % 2 == 0 && ldv % 2 == 0 && al(p) && al(q) && al(r);
+}
+
 hipError_t k_dots2(const double* V, int64_t ldv, int k, const double* a, const double* b, int64_t n,
                    double* partial, double* out, hipStream_t s) {
     const int slots = 2 * k + 3;
     const int nblk = (int)std::min<int64_t>(std::min<int64_t>(1024, 65536 / slots),
                                             std::max<int64_t>(1, (n + 255) / 256));
     const int tiles = std::max(1, (k + MD_TILE - 1) / MD_TILE);
-    hipLaunchKernelGGL(k_dots2_partial, dim3(tiles, nblk), dim3(256), 0, s, V, ldv, k, a, b, n, partial);
+    if (pair_aligned(n, ldv, V, a, b))
+        hipLaunchKernelGGL(k_dots2_partial<2>, dim3(tiles, nblk), dim3(256), 0, s, V, ldv, k, a, b, n, partial);
+    else
+        hipLaunchKernelGGL(k_dots2_partial<1>, dim3(tiles, nblk), dim3(256), 0, s, V, ldv, k, a, b, n, partial);
     hipLaunchKernelGGL(k_sum_slots, dim3(slots), dim3(256), 0, s, partial, nblk, out);
     return hipGetLastError();
 }
 
 hipError_t k_dcgs_update(double* V, int64_t ldv, int k, const double* c, const double* d, const double* w,
                          double inv_alpha, double ecoef, double inv_s, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_dcgs_update_t, grid1(n), dim3(256), 0, s, V, ldv, k, c, d, w, inv_alpha, ecoef,
-                       inv_s, n);
+    if (pair_aligned(n, ldv, V, w, w))
+        hipLaunchKernelGGL(k_dcgs_update_t<2>, grid1((n + 1) / 2), dim3(256), 0, s, V, ldv, k, c, d, w,
+                           inv_alpha, ecoef, inv_s, n);
+    else
+        hipLaunchKernelGGL(k_dcgs_update_t<1>, grid1(n), dim3(256), 0, s, V, ldv, k, c, d, w, inv_alpha,
+                           ecoef, inv_s, n);
     return hipGetLastError();
 }
 

@@ -155,6 +155,66 @@ def test_fgmres_solve_3d_high_contrast(prec):
         P.close()
 
 
+_RESTART_CASE = {}
+
+
+def _restart_case():
+    """32^3 sinkers, two smoothing steps each way.  Its residual history is
+    well conditioned over 45 iterations for every restart length tested: a
+    1e-12 relative perturbation of each preconditioned vector moves the
+    oracle's history by at most ~3e-11.  (The 16^3 sphere with one step is
+    not: its history past iteration ~25 of a 33-vector cycle moves by
+    percents under 1e-14 perturbations, and cannot be compared.)"""
+    if not _RESTART_CASE:
+        w = small_workload("sinker_3d", 4)
+        b = iss_inputs.random_rhs(3, w["n"], seed=9)
+        H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"],
+                         "interface", nu1=2, nu2=2)
+        _RESTART_CASE.update(w=w, b=b, H=H)
+    return _RESTART_CASE["w"], _RESTART_CASE["b"], _RESTART_CASE["H"]
+
+
+@pytest.mark.parametrize("restart", [5, 16, 17, 33])
+def test_fgmres_restart_cycles_match_oracle(restart):
+    """Restarted FGMRES over several cycles: the residual history (the last
+    entry of each cycle being the true residual) follows the oracle's
+    restarted FGMRES (modified Gram-Schmidt) to 1e-6.  The restart lengths
+    put the basis on either side of the 16-vector tiles of the Gram-Schmidt
+    kernels (partial, one full, one full plus one vector, two full plus
+    one)."""
+    import torch
+    w, b, H = _restart_case()
+    _, hist = mg.solve_fgmres(H, b, rtol=1e-11, restart=restart, maxit=45)
+    P = gpu_problem(w, outer="fgmres", restart=restart, nu1=2, nu2=2)
+    x = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
+    info = P.solve("interface", x, to_dev(b), rtol=1e-11, maxit=45, raise_on_fail=False)
+    g = np.array(info["history"])
+    assert len(g) == len(hist) == 46, (len(g), len(hist))
+    assert np.allclose(g, hist, rtol=1e-6, atol=0), np.abs(g / hist - 1).max()
+    P.close()
+
+
+def test_fgmres_2d_odd_length_matches_oracle():
+    """2D FGMRES: 3 x 65^2 unknowns, an odd vector length, so the
+    Gram-Schmidt kernels take their one-element-per-lane path; restart 17
+    gives one restart.  A 1e-12 relative perturbation of the preconditioned
+    vectors moves the oracle's history by ~3e-7: compared to 1e-5."""
+    import torch
+    w = small_workload("square_split_2d", 6)
+    b = iss_inputs.random_rhs(2, w["n"], seed=9)
+    H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"],
+                     "interface", nu1=1, nu2=1)
+    _, hist = mg.solve_fgmres(H, b, rtol=1e-10, restart=17, maxit=45)
+    P = gpu_problem(w, outer="fgmres", restart=17, nu1=1, nu2=1)
+    assert P.vector_size() % 2 == 1
+    x = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
+    info = P.solve("interface", x, to_dev(b), rtol=1e-10, maxit=45, raise_on_fail=False)
+    g = np.array(info["history"])
+    assert len(g) == len(hist) > 18, (len(g), len(hist))
+    assert np.allclose(g, hist, rtol=1e-5, atol=0), np.abs(g / hist - 1).max()
+    P.close()
+
+
 @pytest.mark.parametrize("name,levels", [("sphere_3d", 4), ("sinker_3d", 3)])
 def test_vcycle_default_configuration(name, levels):
     """The benchmark's configuration: averaged (Galerkin) coarse viscosity,
