@@ -766,7 +766,7 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bo
     const int extra = p->opt.nu_inc * (p->levels - l);      // V_var: more steps on coarser levels
     const int nu1 = p->opt.nu1 + extra, nu2 = p->opt.nu2 + extra;
     for (int i = 0; i < nu1; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s));
     ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
     ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
     ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
@@ -776,7 +776,7 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bo
     if (nu2 > 0) {
         ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
         for (int i = 0; i < nu2; ++i)
-            ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
+            ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s));
         ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
     }
     return ISS_OK;
@@ -1244,7 +1244,7 @@ int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps, void* 
     ISS_HIP(k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s));
     ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
     for (int i = 0; i < nsteps; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s));
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s));
     ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
     return ISS_OK;
 }
@@ -1284,7 +1284,7 @@ int iss_smooth_timed(iss_problem* p, int form, int level, int prec, int nsteps, 
     if (e == hipSuccess) e = k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s);
     for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
         e = hipEventRecord(st0, s);
-        if (e == hipSuccess) e = k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, s, &tm);
+        if (e == hipSuccess) e = k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s, &tm);
         if (e == hipSuccess) e = hipEventRecord(st1, s);
         if (e == hipSuccess) e = hipEventSynchronize(st1);
         float t = 0;

@@ -55,10 +55,12 @@ struct PhaseTimer {
     hipEvent_t begin[8], end[8];
 };
 // one Uzawa step on split-layout vectors xs, bs (d+1 fields of Ns each);
-// ws holds d+1 split fields of scratch; tm (optional) times the bulk
-// velocity colour phases
+// ws holds d+1 split fields of scratch.  first_step: the first step of a
+// sequence on these buffers (clears the pressure correction field of ws;
+// later steps rely on the previous step having left it cleared).  tm
+// (optional) times the bulk velocity colour phases
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs,
-                         const void* bs, void* ws, hipStream_t s, PhaseTimer* tm = nullptr);
+                         const void* bs, void* ws, bool first_step, hipStream_t s, PhaseTimer* tm = nullptr);
 // canonical <-> split copy of nf fields (dir SPLIT_PACK: canonical in, split
 // out with zero padding; SPLIT_UNPACK: split in, canonical out)
 hipError_t k_split(const LevelView& L, int prec, int nf, const void* in, void* out, int dir,

@@ -550,9 +550,11 @@ __device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colo
     return true;
 }
 
-// all-interior pass: interior vertex at row position r (run s)
+// all-interior pass: interior vertex at row position r (run s) and its
+// colour (i + j + k) mod (d + 1)
 template <int D>
-__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t bid, int& s, int64_t& v) {
+__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t bid, int& s, int64_t& v,
+                                                 int& colour) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
     int r, j, k;
@@ -561,6 +563,7 @@ __device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t bid
     const int i = M * (r - s * L.q) + s;
     if (i < 1 || i > m) return false;
     v = (int64_t)k * L.Pp + (int64_t)j * L.Rp + r;
+    colour = (i + j + k) % M;
     return true;
 }
 
@@ -826,11 +829,11 @@ __device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int6
 }
 
 template <int D, int F, bool BWD, typename T>
-__device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colour, int64_t bid,
+__device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colour, int64_t rel,
                                                     T* __restrict__ xs, const T* __restrict__ bs) {
     using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t sp = L.spec_off[colour] + bid * 256 + threadIdx.x;
+    const int64_t sp = L.spec_off[colour] + rel;
     if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
     vertex_ijk<D>(L, L.spec[sp], ijk);
@@ -858,14 +861,35 @@ __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colo
 // Gauss-Seidel on C delta = s from delta = 0.  One vertex per thread: the
 // 15-point rows of four fields are too many live values for the grouped
 // form used by the velocity right-hand side.
+//
+// The first colour phase of the sweep is folded into this pass: every
+// neighbour of a colour-0 vertex has another colour and still holds
+// delta = 0, so its update is s / (C_vv) and s need not be stored.  The
+// special rows of colour 0 (element loops, their own s) read only
+// neighbours of other colours and write only their own delta, so on small
+// levels they run as extra workgroups of the same grid (MERGED, blocks >=
+// nbulk); elsewhere as their own launch, which keeps this kernel at half the
+// registers of the element loop.
 template <int D, typename T>
+__device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t rel,
+                                                  const T* __restrict__ xs, const T* __restrict__ bs,
+                                                  T* __restrict__ delta);
+
+template <int D, typename T, bool MERGED>
 __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
-                                                 const T* __restrict__ bs, T* __restrict__ sres) {
+                                                 const T* __restrict__ bs, T* __restrict__ sres,
+                                                 T* __restrict__ delta, int64_t nbulk) {
     using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
-    int s;
+    if constexpr (MERGED) {
+        if ((int64_t)blockIdx.x >= nbulk) {
+            gs_p_special_body<D, T>(L, 0, ((int64_t)blockIdx.x - nbulk) * 256 + threadIdx.x, xs, bs, delta);
+            return;
+        }
+    }
+    int s, colour;
     int64_t v;
-    if (!split_all_vertex<D>(L, blockIdx.x, s, v)) return;
+    if (!split_all_vertex<D>(L, blockIdx.x, s, v, colour)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -883,7 +907,9 @@ __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restric
 #pragma unroll
     for (int o = 1; o <= 2 * D; ++o) cp += E.Sc[o] * P[0][o];
     const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
-    sres[v] = (T)((C)L.sB * dv - sci * cp - bp);
+    const C sv = (C)L.sB * dv - sci * cp - bp;
+    if (colour == 0) delta[v] = (T)(sv / (sci * E.Sc[0]));
+    else sres[v] = (T)sv;
 }
 
 template <int D, typename T>
@@ -909,12 +935,12 @@ __device__ __forceinline__ void gs_p_body(const LevelView& L, int colour, int64_
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t bid,
+__device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t rel,
                                                   const T* __restrict__ xs, const T* __restrict__ bs,
                                                   T* __restrict__ delta) {
     using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
-    const int64_t sp = L.spec_off[colour] + bid * 256 + threadIdx.x;
+    const int64_t sp = L.spec_off[colour] + rel;
     if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
     vertex_ijk<D>(L, L.spec[sp], ijk);
@@ -932,6 +958,14 @@ __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour
 // One colour phase, three launch shapes: bulk only, special only, and both
 // in one grid (bulk workgroups first) for small levels, where the launch
 // latency of two kernels costs more than the lower occupancy of the merged one.
+// The velocity special-only kernel uses one-wave workgroups: its lists start
+// with boundary vertices, which exit at once (Dirichlet), so with one wave
+// per workgroup the scattered interface rows spread over every CU instead of
+// the last few hundred 4-wave groups.  In the pressure kernel every row does
+// work; long lists keep 4-wave groups (neighbouring boundary rows share a
+// CU's L1), short ones use one wave per group to reach more CUs.
+constexpr int SPEC_WG = 64;
+constexpr int64_t SPEC_P_LONG = 65536;   // pressure special rows per colour above which 4-wave groups are used
 template <int D, int F, bool BWD, typename T>
 __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
                                                   const T* __restrict__ g) {
@@ -939,9 +973,9 @@ __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __
 }
 
 template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_special_s(LevelView L, int colour, T* __restrict__ xs,
-                                                          const T* __restrict__ bs) {
-    gs_vel_special_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, bs);
+__global__ __launch_bounds__(SPEC_WG) void k_gs_vel_special_s(LevelView L, int colour, T* __restrict__ xs,
+                                                              const T* __restrict__ bs) {
+    gs_vel_special_body<D, F, BWD, T>(L, colour, (int64_t)blockIdx.x * SPEC_WG + threadIdx.x, xs, bs);
 }
 
 template <int D, int F, bool BWD, typename T>
@@ -949,7 +983,7 @@ __global__ __launch_bounds__(256) void k_gs_vel_m(LevelView L, int colour, T* __
                                                   const T* __restrict__ g, const T* __restrict__ bs,
                                                   int64_t nbulk) {
     if ((int64_t)blockIdx.x < nbulk) gs_vel_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, g);
-    else gs_vel_special_body<D, F, BWD, T>(L, colour, (int64_t)blockIdx.x - nbulk, xs, bs);
+    else gs_vel_special_body<D, F, BWD, T>(L, colour, ((int64_t)blockIdx.x - nbulk) * 256 + threadIdx.x, xs, bs);
 }
 
 template <int D, typename T>
@@ -958,10 +992,10 @@ __global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T
     gs_p_body<D, T>(L, colour, blockIdx.x, sres, delta);
 }
 
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_special_s(LevelView L, int colour, const T* __restrict__ xs,
-                                                        const T* __restrict__ bs, T* __restrict__ delta) {
-    gs_p_special_body<D, T>(L, colour, blockIdx.x, xs, bs, delta);
+template <int D, typename T, int WG>
+__global__ __launch_bounds__(WG) void k_gs_p_special_s(LevelView L, int colour, const T* __restrict__ xs,
+                                                       const T* __restrict__ bs, T* __restrict__ delta) {
+    gs_p_special_body<D, T>(L, colour, (int64_t)blockIdx.x * WG + threadIdx.x, xs, bs, delta);
 }
 
 template <int D, typename T>
@@ -969,14 +1003,19 @@ __global__ __launch_bounds__(256) void k_gs_p_m(LevelView L, int colour, const T
                                                 const T* __restrict__ xs, const T* __restrict__ bs,
                                                 T* __restrict__ delta, int64_t nbulk) {
     if ((int64_t)blockIdx.x < nbulk) gs_p_body<D, T>(L, colour, blockIdx.x, sres, delta);
-    else gs_p_special_body<D, T>(L, colour, (int64_t)blockIdx.x - nbulk, xs, bs, delta);
+    else gs_p_special_body<D, T>(L, colour, ((int64_t)blockIdx.x - nbulk) * 256 + threadIdx.x, xs, bs, delta);
 }
 
+// p += w d, then d = 0: the pressure correction of a smoothing step is
+// applied and its buffer left cleared for the next step's sweep
 template <typename T>
-__global__ void k_axpy_field(T* __restrict__ p, const T* __restrict__ d, typename Acc<T>::type w, int64_t n) {
+__global__ void k_axpy_clear(T* __restrict__ p, T* __restrict__ d, typename Acc<T>::type w, int64_t n) {
     using C = typename Acc<T>::type;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) p[e] = (T)((C)p[e] + w * (C)d[e]);
+    if (e < n) {
+        p[e] = (T)((C)p[e] + w * (C)d[e]);
+        d[e] = (T)(C)0;
+    }
 }
 
 template <typename T>
@@ -1432,7 +1471,7 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
     return hipMemcpyToSymbol(HIP_SYMBOL(g_e2f), t32, bytes32);
 }
 
-static inline int64_t special_blocks(int64_t ns) { return (ns + 255) / 256; }
+static inline int64_t special_blocks(int64_t ns, int wg = 256) { return (ns + wg - 1) / wg; }
 
 template <int D, int F, int BLK, int MODE, typename T>
 static hipError_t apply_t(const LevelView& L, const T* x, const T* b, T* y, hipStream_t s) {
@@ -1474,13 +1513,16 @@ constexpr int MERGE_MAX_N = 64;
 
 // One Uzawa step (eq. Uzawa_smooth) on split-layout vectors: symmetric
 // velocity sweep (forward colours 0..d, backward d..0; bulk then special
-// launch per colour), then delta = 0, pressure forward sweep on C,
-// p += omega delta.  ws holds d + 1 split fields: g = f - B^T p in fields
-// 0..d-1 during the velocity sweep, s = B u - C p - g in field 0 and delta in
-// field d during the pressure sweep.
+// launch per colour), then the pressure forward sweep on C from delta = 0
+// (colour 0 inside the s pass), p += omega delta.  ws holds d + 1 split
+// fields: g = f - B^T p in fields 0..d-1 during the velocity sweep,
+// s = B u - C p - g in field 0 and delta in field d during the pressure
+// sweep.  Each step leaves delta cleared; the first step of a sequence
+// (first_step) clears it itself, so a sequence never depends on what an
+// earlier call left in ws.
 template <int D, int F, typename T>
-static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs, T* ws, hipStream_t s,
-                           PhaseTimer* tm) {
+static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs, T* ws, bool first_step,
+                           hipStream_t s, PhaseTimer* tm) {
     const int64_t ba = split_slab_blocks<D>(L.n, (L.n - 1) / (D + 1) + 1);   // grouped (velocity rhs)
     const int64_t bp = split_slab_blocks<D>(L.n, L.Rp);                      // one vertex per thread
     const int64_t bc = split_slab_blocks<D>(L.n, (L.n - 1) / (D + 1) + 1);
@@ -1494,6 +1536,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
         for (int cc = 0; cc <= D; ++cc) {
             const int c = pass == 0 ? cc : D - cc;
             const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
+            const int64_t nsw = special_blocks(L.spec_off[c + 1] - L.spec_off[c], SPEC_WG);
             if (tm) (void)hipEventRecord(tm->begin[pass * (D + 1) + cc], s);
             if (merge && bc > 0 && ns > 0) {
                 if (pass == 0)
@@ -1506,49 +1549,63 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                     hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
                 if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
                 if (ns > 0)
-                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs);
+                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L, c, xs, bs);
             } else {
                 if (bc > 0)
                     hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
                 if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
                 if (ns > 0)
-                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs);
+                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L, c, xs, bs);
             }
         }
     }
-    hipLaunchKernelGGL((k_fill_t<T>), grid1(L.Ns), dim3(256), 0, s, delta, L.Ns, (typename Acc<T>::type)0);
-    if (ba > 0)
-        hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3((unsigned)bp), dim3(256), 0, s, L, xs, bs, sres);
+    if (first_step)
+        hipLaunchKernelGGL((k_fill_t<T>), grid1(L.Ns), dim3(256), 0, s, delta, L.Ns, (typename Acc<T>::type)0);
     for (int c = 0; c <= D; ++c) {
         const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
-        if (merge && bc > 0 && ns > 0) {
+        const int64_t nsw = special_blocks(L.spec_off[c + 1] - L.spec_off[c], SPEC_WG);
+        if (c == 0) {
+            // s pass with colour 0 folded in
+            const int64_t nb = ba > 0 ? bp : 0;
+            if (merge && nb + ns > 0) {
+                hipLaunchKernelGGL((k_p_rhs_s<D, T, true>), dim3((unsigned)(nb + ns)), dim3(256), 0, s, L, xs, bs,
+                                   sres, delta, nb);
+                continue;
+            }
+            if (nb > 0)
+                hipLaunchKernelGGL((k_p_rhs_s<D, T, false>), dim3((unsigned)nb), dim3(256), 0, s, L, xs, bs, sres,
+                                   delta, nb);
+        } else if (merge && bc > 0 && ns > 0) {
             hipLaunchKernelGGL((k_gs_p_m<D, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, sres, xs, bs, delta, bc);
             continue;
-        }
-        if (bc > 0)
+        } else if (bc > 0) {
             hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, sres, delta);
-        if (ns > 0)
-            hipLaunchKernelGGL((k_gs_p_special_s<D, T>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
+        }
+        if (ns > 0 && L.spec_off[c + 1] - L.spec_off[c] > SPEC_P_LONG)
+            hipLaunchKernelGGL((k_gs_p_special_s<D, T, 256>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
+        else if (ns > 0)
+            hipLaunchKernelGGL((k_gs_p_special_s<D, T, SPEC_WG>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L, c, xs,
+                               bs, delta);
     }
-    hipLaunchKernelGGL((k_axpy_field<T>), grid1(L.Ns), dim3(256), 0, s, xs + (int64_t)D * L.Ns, delta,
+    hipLaunchKernelGGL((k_axpy_clear<T>), grid1(L.Ns), dim3(256), 0, s, xs + (int64_t)D * L.Ns, delta,
                        (typename Acc<T>::type)omega, L.Ns);
     return hipGetLastError();
 }
 
 template <int D, typename T>
 static hipError_t smooth_d(const LevelView& L, int form, double omega, T* xs, const T* bs, T* ws,
-                           hipStream_t s, PhaseTimer* tm) {
-    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, xs, bs, ws, s, tm);
-    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, xs, bs, ws, s, tm);
-    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, xs, bs, ws, s, tm);
+                           bool first_step, hipStream_t s, PhaseTimer* tm) {
+    if (form == FORM_GRADIENT) return smooth_t<D, 0, T>(L, omega, xs, bs, ws, first_step, s, tm);
+    if (form == FORM_STRAIN) return smooth_t<D, 1, T>(L, omega, xs, bs, ws, first_step, s, tm);
+    if (form == FORM_INTERFACE) return smooth_t<D, 2, T>(L, omega, xs, bs, ws, first_step, s, tm);
     return hipErrorInvalidValue;
 }
 
 hipError_t k_smooth_step(const LevelView& L, int form, int prec, double omega, void* xs, const void* bs,
-                         void* ws, hipStream_t s, PhaseTimer* tm) {
+                         void* ws, bool first_step, hipStream_t s, PhaseTimer* tm) {
     ISS_BY_PREC(prec,
-        if (L.dim == 3) return smooth_d<3, T>(L, form, omega, (T*)xs, (const T*)bs, (T*)ws, s, tm);
-        return smooth_d<2, T>(L, form, omega, (T*)xs, (const T*)bs, (T*)ws, s, tm))
+        if (L.dim == 3) return smooth_d<3, T>(L, form, omega, (T*)xs, (const T*)bs, (T*)ws, first_step, s, tm);
+        return smooth_d<2, T>(L, form, omega, (T*)xs, (const T*)bs, (T*)ws, first_step, s, tm))
     return hipErrorInvalidValue;
 }
 
