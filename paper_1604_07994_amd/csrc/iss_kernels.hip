@@ -510,14 +510,15 @@ __device__ __forceinline__ int64_t snb(const LevelView& L, const XOff& xo, int o
 
 // Split-layout passes: the threads of XCD x cover its slab of interior rows
 // with run positions fastest, then rows, then planes.  `per_row` is the
-// number of positions per row the pass visits.  Returns false past the end.
+// number of positions per row the pass visits; bid is a 256-thread group and
+// tid the thread within it.  Returns false past the end.
 template <int D>
-__device__ __forceinline__ bool split_slab_thread(const LevelView& L, int64_t bid, int per_row, int& pos, int& j,
-                                                  int& k) {
+__device__ __forceinline__ bool split_slab_thread(const LevelView& L, int64_t bid, int tid, int per_row, int& pos,
+                                                  int& j, int& k) {
     const int m = L.n - 1;
     const int rows = slab_rows(m);
     const int xcd = (int)(bid & (NXCD - 1));
-    const int64_t g = (bid / NXCD) * 256 + threadIdx.x;
+    const int64_t g = (bid / NXCD) * 256 + tid;
     pos = (int)(g % per_row);
     const int64_t r = g / per_row;
     const int jl = (int)(r % rows);
@@ -536,12 +537,12 @@ inline int64_t split_slab_blocks(int n, int per_row) {
 
 // colour phase: interior vertex of colour `colour` (run s of its row)
 template <int D>
-__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int64_t bid, int& s,
+__device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colour, int64_t bid, int tid, int& s,
                                                     int64_t& v) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
     int t, j, k;
-    if (!split_slab_thread<D>(L, bid, m / M + 1, t, j, k)) return false;
+    if (!split_slab_thread<D>(L, bid, tid, m / M + 1, t, j, k)) return false;
     s = (colour - j - k) % M;
     if (s < 0) s += M;
     const int i = M * t + s;
@@ -553,12 +554,12 @@ __device__ __forceinline__ bool split_colour_vertex(const LevelView& L, int colo
 // all-interior pass: interior vertex at row position r (run s) and its
 // colour (i + j + k) mod (d + 1)
 template <int D>
-__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t bid, int& s, int64_t& v,
+__device__ __forceinline__ bool split_all_vertex(const LevelView& L, int64_t bid, int tid, int& s, int64_t& v,
                                                  int& colour) {
     constexpr int M = D + 1;
     const int m = L.n - 1;
     int r, j, k;
-    if (!split_slab_thread<D>(L, bid, L.Rp, r, j, k)) return false;
+    if (!split_slab_thread<D>(L, bid, tid, L.Rp, r, j, k)) return false;
     s = r / L.q;
     const int i = M * (r - s * L.q) + s;
     if (i < 1 || i > m) return false;
@@ -662,7 +663,7 @@ template <int D>
 __device__ __forceinline__ bool rhs_thread(const LevelView& L, int& t, int& j, int& k, int& tn) {
     const int m = L.n - 1;
     tn = m / (D + 1) + 1;                          // positions covering i = 1..m
-    const bool act = split_slab_thread<D>(L, blockIdx.x, tn, t, j, k);
+    const bool act = split_slab_thread<D>(L, blockIdx.x, threadIdx.x, tn, t, j, k);
     if (!act) {                                    // keep the lane for the shuffles
         j = m;
         k = (D == 3) ? m : 0;
@@ -772,13 +773,13 @@ __global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restr
 }
 
 template <int D, int F, bool BWD, typename T>
-__device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int64_t bid, T* __restrict__ xs,
-                                            const T* __restrict__ g) {
+__device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int64_t bid, int tid,
+                                            T* __restrict__ xs, const T* __restrict__ g) {
     using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     int s;
     int64_t v;
-    if (!split_colour_vertex<D>(L, colour, bid, s, v)) return;
+    if (!split_colour_vertex<D>(L, colour, bid, tid, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     // every load is issued before the phase test (all addresses are
@@ -867,29 +868,34 @@ __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colo
 // delta = 0, so its update is s / (C_vv) and s need not be stored.  The
 // special rows of colour 0 (element loops, their own s) read only
 // neighbours of other colours and write only their own delta, so on small
-// levels they run as extra workgroups of the same grid (MERGED, blocks >=
-// nbulk); elsewhere as their own launch, which keeps this kernel at half the
-// registers of the element loop.
+// levels they run in the same grid (MERGED: one-wave workgroups, four per
+// 256-thread bulk group, special rows from workgroup 4 nbulk on); elsewhere
+// as their own launch, which keeps this kernel at half the registers of the
+// element loop.
 template <int D, typename T>
 __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t rel,
                                                   const T* __restrict__ xs, const T* __restrict__ bs,
                                                   T* __restrict__ delta);
 
 template <int D, typename T, bool MERGED>
-__global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
-                                                 const T* __restrict__ bs, T* __restrict__ sres,
-                                                 T* __restrict__ delta, int64_t nbulk) {
+__global__ __launch_bounds__(MERGED ? 64 : 256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
+                                                               const T* __restrict__ bs, T* __restrict__ sres,
+                                                               T* __restrict__ delta, int64_t nbulk) {
     using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
+    int64_t bid = blockIdx.x;
+    int tid = threadIdx.x;
     if constexpr (MERGED) {
-        if ((int64_t)blockIdx.x >= nbulk) {
-            gs_p_special_body<D, T>(L, 0, ((int64_t)blockIdx.x - nbulk) * 256 + threadIdx.x, xs, bs, delta);
+        if (bid >= 4 * nbulk) {
+            gs_p_special_body<D, T>(L, 0, (bid - 4 * nbulk) * 64 + tid, xs, bs, delta);
             return;
         }
+        tid += (int)(bid & 3) * 64;
+        bid >>= 2;
     }
     int s, colour;
     int64_t v;
-    if (!split_all_vertex<D>(L, blockIdx.x, s, v, colour)) return;
+    if (!split_all_vertex<D>(L, bid, tid, s, v, colour)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -913,12 +919,12 @@ __global__ __launch_bounds__(256) void k_p_rhs_s(LevelView L, const T* __restric
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void gs_p_body(const LevelView& L, int colour, int64_t bid, const T* __restrict__ sres,
-                                          T* __restrict__ delta) {
+__device__ __forceinline__ void gs_p_body(const LevelView& L, int colour, int64_t bid, int tid,
+                                          const T* __restrict__ sres, T* __restrict__ delta) {
     using C = typename Acc<T>::type;
     int s;
     int64_t v;
-    if (!split_colour_vertex<D>(L, colour, bid, s, v)) return;
+    if (!split_colour_vertex<D>(L, colour, bid, tid, s, v)) return;
     const XOff xo = x_offsets<D>(L, s);
     const auto& E = ETab<D, C>::get();
     const int ph = L.vphase_s[v];
@@ -956,8 +962,10 @@ __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour
 }
 
 // One colour phase, three launch shapes: bulk only, special only, and both
-// in one grid (bulk workgroups first) for small levels, where the launch
-// latency of two kernels costs more than the lower occupancy of the merged one.
+// in one grid for small levels, where the launch latency of two kernels
+// costs more than the lower occupancy of the merged one.  The merged grid is
+// made of one-wave workgroups: four per 256-thread bulk group first, then
+// the special rows.
 // The velocity special-only kernel uses one-wave workgroups: its lists start
 // with boundary vertices, which exit at once (Dirichlet), so with one wave
 // per workgroup the scattered interface rows spread over every CU instead of
@@ -969,7 +977,7 @@ constexpr int64_t SPEC_P_LONG = 65536;   // pressure special rows per colour abo
 template <int D, int F, bool BWD, typename T>
 __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
                                                   const T* __restrict__ g) {
-    gs_vel_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, g);
+    gs_vel_body<D, F, BWD, T>(L, colour, blockIdx.x, threadIdx.x, xs, g);
 }
 
 template <int D, int F, bool BWD, typename T>
@@ -979,17 +987,18 @@ __global__ __launch_bounds__(SPEC_WG) void k_gs_vel_special_s(LevelView L, int c
 }
 
 template <int D, int F, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_gs_vel_m(LevelView L, int colour, T* __restrict__ xs,
-                                                  const T* __restrict__ g, const T* __restrict__ bs,
-                                                  int64_t nbulk) {
-    if ((int64_t)blockIdx.x < nbulk) gs_vel_body<D, F, BWD, T>(L, colour, blockIdx.x, xs, g);
-    else gs_vel_special_body<D, F, BWD, T>(L, colour, ((int64_t)blockIdx.x - nbulk) * 256 + threadIdx.x, xs, bs);
+__global__ __launch_bounds__(64) void k_gs_vel_m(LevelView L, int colour, T* __restrict__ xs,
+                                                 const T* __restrict__ g, const T* __restrict__ bs,
+                                                 int64_t nbulk) {
+    const int64_t b = blockIdx.x;
+    if (b < 4 * nbulk) gs_vel_body<D, F, BWD, T>(L, colour, b >> 2, (int)(b & 3) * 64 + threadIdx.x, xs, g);
+    else gs_vel_special_body<D, F, BWD, T>(L, colour, (b - 4 * nbulk) * 64 + threadIdx.x, xs, bs);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T* __restrict__ sres,
                                                 T* __restrict__ delta) {
-    gs_p_body<D, T>(L, colour, blockIdx.x, sres, delta);
+    gs_p_body<D, T>(L, colour, blockIdx.x, threadIdx.x, sres, delta);
 }
 
 template <int D, typename T, int WG>
@@ -999,11 +1008,12 @@ __global__ __launch_bounds__(WG) void k_gs_p_special_s(LevelView L, int colour, 
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_gs_p_m(LevelView L, int colour, const T* __restrict__ sres,
-                                                const T* __restrict__ xs, const T* __restrict__ bs,
-                                                T* __restrict__ delta, int64_t nbulk) {
-    if ((int64_t)blockIdx.x < nbulk) gs_p_body<D, T>(L, colour, blockIdx.x, sres, delta);
-    else gs_p_special_body<D, T>(L, colour, ((int64_t)blockIdx.x - nbulk) * 256 + threadIdx.x, xs, bs, delta);
+__global__ __launch_bounds__(64) void k_gs_p_m(LevelView L, int colour, const T* __restrict__ sres,
+                                               const T* __restrict__ xs, const T* __restrict__ bs,
+                                               T* __restrict__ delta, int64_t nbulk) {
+    const int64_t b = blockIdx.x;
+    if (b < 4 * nbulk) gs_p_body<D, T>(L, colour, b >> 2, (int)(b & 3) * 64 + threadIdx.x, sres, delta);
+    else gs_p_special_body<D, T>(L, colour, (b - 4 * nbulk) * 64 + threadIdx.x, xs, bs, delta);
 }
 
 // p += w d, then d = 0: the pressure correction of a smoothing step is
@@ -1540,9 +1550,11 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             if (tm) (void)hipEventRecord(tm->begin[pass * (D + 1) + cc], s);
             if (merge && bc > 0 && ns > 0) {
                 if (pass == 0)
-                    hipLaunchKernelGGL((k_gs_vel_m<D, F, false, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, xs, g, bs, bc);
+                    hipLaunchKernelGGL((k_gs_vel_m<D, F, false, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c,
+                                       xs, g, bs, bc);
                 else
-                    hipLaunchKernelGGL((k_gs_vel_m<D, F, true, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, xs, g, bs, bc);
+                    hipLaunchKernelGGL((k_gs_vel_m<D, F, true, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c,
+                                       xs, g, bs, bc);
                 if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
             } else if (pass == 0) {
                 if (bc > 0)
@@ -1568,7 +1580,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             // s pass with colour 0 folded in
             const int64_t nb = ba > 0 ? bp : 0;
             if (merge && nb + ns > 0) {
-                hipLaunchKernelGGL((k_p_rhs_s<D, T, true>), dim3((unsigned)(nb + ns)), dim3(256), 0, s, L, xs, bs,
+                hipLaunchKernelGGL((k_p_rhs_s<D, T, true>), dim3((unsigned)(4 * nb + nsw)), dim3(64), 0, s, L, xs, bs,
                                    sres, delta, nb);
                 continue;
             }
@@ -1576,7 +1588,8 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                 hipLaunchKernelGGL((k_p_rhs_s<D, T, false>), dim3((unsigned)nb), dim3(256), 0, s, L, xs, bs, sres,
                                    delta, nb);
         } else if (merge && bc > 0 && ns > 0) {
-            hipLaunchKernelGGL((k_gs_p_m<D, T>), dim3((unsigned)(bc + ns)), dim3(256), 0, s, L, c, sres, xs, bs, delta, bc);
+            hipLaunchKernelGGL((k_gs_p_m<D, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c, sres, xs, bs,
+                               delta, bc);
             continue;
         } else if (bc > 0) {
             hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, sres, delta);
