@@ -192,7 +192,18 @@ int iss_prolong_add(iss_problem* p, int level, int prec, const void* ec, void* x
 int iss_coarse_solve(iss_problem* p, int form, const double* b, double* x,
                      iss_stream_t stream);
 
-/* One V(nu1, nu2) cycle on the finest level, in place on x. */
+/* One V(nu1, nu2) cycle on the finest level, in place on x.
+ *
+ * The part of the cycle below the finest level works only on the
+ * library's own per-level buffers.  Its first run for a (coarse form,
+ * precision) pair is eager; the second records it once as a HIP graph (on
+ * an internal non-blocking stream) and every later cycle, here and inside
+ * iss_solve, replays that graph on `stream`: the same kernels with the
+ * same arguments, so the results are bitwise those of eager launches.
+ * Setting ISS_VCYCLE_GRAPH=0 in the environment before iss_problem_create
+ * keeps every launch eager; if recording fails the problem falls back to
+ * eager launches by itself.  Cycles of one problem must not run
+ * concurrently on several streams (they share the per-level buffers). */
 int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b,
                iss_stream_t stream);
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -202,6 +203,12 @@ struct Coarse {
 
 }  // namespace
 
+// the part of a V-cycle below the finest level, recorded once as a HIP graph
+struct VGraph {
+    bool warm = false;              // one eager run done (buffers and coarse inverse exist)
+    hipGraphExec_t exec = nullptr;
+};
+
 struct iss_problem {
     int dim = 3, macro = 1, levels = 0, coarse = 0;
     std::vector<iss_inclusion> inc;
@@ -230,6 +237,11 @@ struct iss_problem {
     int64_t reorth_count = 0;       // second Gram-Schmidt passes (diagnostics)
     iss_net* net = nullptr;         // attached band correction (not owned)
     int net_accepted = 0, net_rejected = 0;
+    // coarse part of the V-cycle per (form, precision) as a HIP graph;
+    // ISS_VCYCLE_GRAPH=0 in the environment at creation turns it off
+    bool use_graphs = true;
+    VGraph vgraph[3][3];
+    hipStream_t cap_stream = nullptr;
     std::vector<void*> allocs;
 };
 
@@ -751,6 +763,48 @@ int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hip
 // V(nu1, nu2) cycle on level l.  x_zero: x holds zero on entry (it is then
 // not read).  Smoothing runs on colour-split copies of x and b; b is packed
 // once for both smoothing phases.
+int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bool x_zero, hipStream_t s);
+
+// The V-cycle below the finest level touches only the library's per-level
+// buffers (restricted residual in, correction out), so after one eager run,
+// which allocates them and the coarse inverse, it is recorded once per
+// (form, precision) as a HIP graph on a capture stream and replayed on the
+// caller's stream: one launch instead of about 1500 short ones per cycle.
+// The recording holds kernel launches only (buffers are cleared by fill
+// kernels).  If recording fails the problem falls back to eager launches.
+int coarse_part(iss_problem* p, int l, int form, int prec, hipStream_t s, bool top) {
+    Level& Lc = p->lv[l];
+    if (!top || !p->use_graphs || l == p->coarse)
+        return vcycle(p, l, form, prec, Lc.w_x[prec], Lc.w_b[prec], true, s);
+    VGraph& G = p->vgraph[form][prec];
+    if (!G.exec) {
+        if (!G.warm) {
+            const int rc = vcycle(p, l, form, prec, Lc.w_x[prec], Lc.w_b[prec], true, s);
+            if (rc == ISS_OK) G.warm = true;
+            return rc;
+        }
+        hipError_t e = hipSuccess;
+        if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        int rc = ISS_OK;
+        hipGraph_t g = nullptr;
+        if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            rc = vcycle(p, l, form, prec, Lc.w_x[prec], Lc.w_b[prec], true, p->cap_stream);
+            e = hipStreamEndCapture(p->cap_stream, &g);
+        }
+        if (rc == ISS_OK && e == hipSuccess && g) e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != ISS_OK || e != hipSuccess || !G.exec) {
+            G.exec = nullptr;
+            p->use_graphs = false;
+            (void)hipGetLastError();
+            return vcycle(p, l, form, prec, Lc.w_x[prec], Lc.w_b[prec], true, s);
+        }
+    }
+    ISS_HIP(hipGraphLaunch(G.exec, s));
+    return ISS_OK;
+}
+
 int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bool x_zero, hipStream_t s) {
     if (l == p->coarse) return coarse_solve(p, form, prec, b, x, s);
     int rc;
@@ -771,7 +825,7 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bo
     ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
     ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
     const int cform = (p->opt.coarse_form >= 0) ? p->opt.coarse_form : form;
-    if ((rc = vcycle(p, l - 1, cform, prec, Lc.w_x[prec], Lc.w_b[prec], true, s))) return rc;
+    if ((rc = coarse_part(p, l - 1, cform, prec, s, l == p->levels))) return rc;
     ISS_HIP(k_prolong_add(L.v, Lc.v, prec, Lc.w_x[prec], x, s));
     if (nu2 > 0) {
         ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
@@ -1059,6 +1113,10 @@ int iss_default_options(iss_options* o) {
 void iss_problem_destroy(iss_problem* p) {
     if (!p) return;
     if (p->net) p->net->p = nullptr;
+    for (auto& row : p->vgraph)
+        for (auto& G : row)
+            if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (void* q : p->allocs) (void)hipFree(q);
     if (p->h_pinned) (void)hipHostFree(p->h_pinned);
     delete p;
@@ -1097,6 +1155,10 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     p->mu.resize(256, 1.0);
     if (opt) p->opt = *opt;
     else iss_default_options(&p->opt);
+    {
+        const char* g = std::getenv("ISS_VCYCLE_GRAPH");
+        p->use_graphs = !(g && std::strcmp(g, "0") == 0);
+    }
     if (p->opt.nu1 < 0 || p->opt.nu2 < 0 || p->opt.nu_inc < 0 || !(p->opt.stab_beta > 0) || p->opt.restart < 1 ||
         (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES) ||
         (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
