@@ -772,6 +772,93 @@ __global__ __launch_bounds__(256) void k_vel_rhs_s(LevelView L, const T* __restr
     }
 }
 
+// Grouped s pass for the larger levels: a thread owns position t of every
+// run of a row, i.e. the d+1 consecutive vertices i = (d+1) t + q, as in
+// k_vel_rhs_s, so one coalesced load per run and footprint row serves all
+// of them.  The fields are read and accumulated one after another, so only
+// one field's footprint rows are live in registers.  Integer stencils (B times -|T|/(d+1), C times |T|) and the
+// colour-0 update of the first pressure phase as in k_p_rhs_s.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_p_rhs_g(LevelView L, const T* __restrict__ xs,
+                                                 const T* __restrict__ bs, T* __restrict__ sres,
+                                                 T* __restrict__ delta) {
+    using C = typename Acc<T>::type;
+    constexpr int M = D + 1;
+    int t, j, k, tn;
+    const bool act = rhs_thread<D>(L, t, j, k, tn);
+    const int64_t rb0 = (int64_t)k * L.Pp + (int64_t)j * L.Rp;
+    C dv[M], cp[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) { dv[q] = 0; cp[q] = 0; }
+    // velocity fields: a rolled loop (one field's footprint rows live at a
+    // time); the integer weight of component f is a uniform select
+#pragma unroll 1
+    for (int f = 0; f < D; ++f) {
+        static_for<0, rhs_rows<D>()>([&](auto rc) {
+            constexpr int dy = ROW_DY[decltype(rc)::value];
+            constexpr int dz = D == 3 ? ROW_DZ[decltype(rc)::value] : 0;
+            constexpr bool used = row_used<D, 0, 0>(dy, dz) || row_used<D, 0, 1>(dy, dz) ||
+                                  (D == 3 && row_used<D, 0, D - 1>(dy, dz));
+            if constexpr (used) {
+                C v[M + 2];
+                row_runs<D, T, C>(L, xs + (int64_t)f * L.Ns,
+                                  (uint32_t)(rb0 + (int64_t)dy * L.Rp + (int64_t)dz * L.Pp), t, tn, v);
+                static_for<0, M>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    static_for<0, 3>([&](auto xc) {
+                        constexpr int dx = decltype(xc)::value - 1;
+                        constexpr int o = off_index<D>(dx, dy, dz);
+                        if constexpr (o >= 0) {
+                            constexpr int w0 = sdiv_int<D>(0, o), w1 = sdiv_int<D>(1, o);
+                            constexpr int w2 = D == 3 ? sdiv_int<D>(D - 1, o) : 0;
+                            if constexpr (w0 != 0 || w1 != 0 || w2 != 0)
+                                dv[q] += (C)(f == 0 ? w0 : (f == 1 ? w1 : w2)) * v[1 + q + dx];
+                        }
+                    });
+                });
+            }
+        });
+    }
+    // pressure: C rows
+    static_for<0, rhs_rows<D>()>([&](auto rc) {
+        constexpr int dy = ROW_DY[decltype(rc)::value];
+        constexpr int dz = D == 3 ? ROW_DZ[decltype(rc)::value] : 0;
+        if constexpr (row_used<D, 2, 0>(dy, dz)) {
+            C v[M + 2];
+            row_runs<D, T, C>(L, xs + (int64_t)D * L.Ns, (uint32_t)(rb0 + (int64_t)dy * L.Rp + (int64_t)dz * L.Pp),
+                              t, tn, v);
+            static_for<0, M>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                static_for<0, 3>([&](auto xc) {
+                    constexpr int dx = decltype(xc)::value - 1;
+                    constexpr int o = off_index<D>(dx, dy, dz);
+                    if constexpr (o >= 0) {
+                        constexpr int w = sc_int<D>(o);
+                        if constexpr (w != 0) cp[q] += (C)w * v[1 + q + dx];
+                    }
+                });
+            });
+        }
+    });
+    if (!act) return;
+    const int m = L.n - 1;
+    const C sdv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
+    const C vol = (C)kuhn_volume<D>();
+    constexpr int c0 = sc_int<D>(0);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const int i = M * t + q;
+        if (i < 1 || i > m) continue;
+        const int64_t v = rb0 + (int64_t)q * L.q + t;
+        const int ph = L.vphase_s[v];
+        if (ph == SPECIAL) continue;
+        const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
+        const C sv = sdv * dv[q] - sci * (vol * cp[q]) - (C)bs[(int64_t)D * L.Ns + v];
+        if ((i + j + k) % M == 0) delta[v] = (T)(sv / (sci * (vol * (C)c0)));
+        else sres[v] = (T)sv;
+    }
+}
+
 template <int D, int F, bool BWD, typename T>
 __device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int64_t bid, int tid,
                                             T* __restrict__ xs, const T* __restrict__ g) {
@@ -859,40 +946,37 @@ __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colo
 
 // Pressure: s = B u - C p - g on interior isoviscous vertices (u and p are
 // fixed during the pressure sweep), then one forward colour sweep of
-// Gauss-Seidel on C delta = s from delta = 0.  One vertex per thread: the
-// 15-point rows of four fields are too many live values for the grouped
-// form used by the velocity right-hand side.
+// Gauss-Seidel on C delta = s from delta = 0.  This form (one vertex per
+// thread, merged with the colour-0 special rows) serves the levels up to
+// 65^3; k_p_rhs_g below serves the larger ones.
 //
 // The first colour phase of the sweep is folded into this pass: every
 // neighbour of a colour-0 vertex has another colour and still holds
 // delta = 0, so its update is s / (C_vv) and s need not be stored.  The
 // special rows of colour 0 (element loops, their own s) read only
-// neighbours of other colours and write only their own delta, so on small
-// levels they run in the same grid (MERGED: one-wave workgroups, four per
-// 256-thread bulk group, special rows from workgroup 4 nbulk on); elsewhere
-// as their own launch, which keeps this kernel at half the registers of the
-// element loop.
+// neighbours of other colours and write only their own delta, so they run
+// in the same grid: one-wave workgroups, four per 256-thread bulk group,
+// special rows from workgroup 4 nbulk on.  (On larger levels they have their
+// own launch, which keeps the s pass at half the registers of the element
+// loop.)
 template <int D, typename T>
 __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour, int64_t rel,
                                                   const T* __restrict__ xs, const T* __restrict__ bs,
                                                   T* __restrict__ delta);
 
-template <int D, typename T, bool MERGED>
-__global__ __launch_bounds__(MERGED ? 64 : 256) void k_p_rhs_s(LevelView L, const T* __restrict__ xs,
-                                                               const T* __restrict__ bs, T* __restrict__ sres,
-                                                               T* __restrict__ delta, int64_t nbulk) {
+template <int D, typename T>
+__global__ __launch_bounds__(64) void k_p_rhs_s(LevelView L, const T* __restrict__ xs, const T* __restrict__ bs,
+                                                T* __restrict__ sres, T* __restrict__ delta, int64_t nbulk) {
     using C = typename Acc<T>::type;
     constexpr int NB = KuhnTables<D>::NB;
     int64_t bid = blockIdx.x;
     int tid = threadIdx.x;
-    if constexpr (MERGED) {
-        if (bid >= 4 * nbulk) {
-            gs_p_special_body<D, T>(L, 0, (bid - 4 * nbulk) * 64 + tid, xs, bs, delta);
-            return;
-        }
-        tid += (int)(bid & 3) * 64;
-        bid >>= 2;
+    if (bid >= 4 * nbulk) {
+        gs_p_special_body<D, T>(L, 0, (bid - 4 * nbulk) * 64 + tid, xs, bs, delta);
+        return;
     }
+    tid += (int)(bid & 3) * 64;
+    bid >>= 2;
     int s, colour;
     int64_t v;
     if (!split_all_vertex<D>(L, bid, tid, s, v, colour)) return;
@@ -1580,13 +1664,12 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             // s pass with colour 0 folded in
             const int64_t nb = ba > 0 ? bp : 0;
             if (merge && nb + ns > 0) {
-                hipLaunchKernelGGL((k_p_rhs_s<D, T, true>), dim3((unsigned)(4 * nb + nsw)), dim3(64), 0, s, L, xs, bs,
+                hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3((unsigned)(4 * nb + nsw)), dim3(64), 0, s, L, xs, bs,
                                    sres, delta, nb);
                 continue;
             }
-            if (nb > 0)
-                hipLaunchKernelGGL((k_p_rhs_s<D, T, false>), dim3((unsigned)nb), dim3(256), 0, s, L, xs, bs, sres,
-                                   delta, nb);
+            if (ba > 0)
+                hipLaunchKernelGGL((k_p_rhs_g<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, sres, delta);
         } else if (merge && bc > 0 && ns > 0) {
             hipLaunchKernelGGL((k_gs_p_m<D, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c, sres, xs, bs,
                                delta, bc);
