@@ -95,17 +95,36 @@ typedef struct {
                            *   of the nested finest-level viscosities (and of
                            *   1/mu for C) -- for nested P1 spaces the coarse
                            *   viscous block is then the Galerkin product
-                           *   P^T A P; averages are binned into <= 254
-                           *   phases per level (< 2% relative width).     */
-    int coarse_form;      /* viscous form used on the levels below the
-                           * finest inside V-cycles: -1 (default) = the form
-                           * of the call; ISS_STRAIN follows the paper's swap
-                           * to the strain form on coarse grids (Sec. 5),
-                           * applied to every coarser level.              */
+                           *   P^T A P.  A level keeps its distinct
+                           *   averages exactly when they fit its 254-entry
+                           *   phase table; otherwise the mixed averages are
+                           *   grouped into <= 250 logarithmic bins (each
+                           *   member takes its bin's mean; relative width
+                           *   below 4% at contrast 1e4), an approximation
+                           *   of the preconditioner only.                 */
+    int coarse_form;      /* viscous form of the coarsest level inside
+                           * V-cycles (Sec. 5 swaps a_tr for the strain form
+                           * on the coarse grid): -1 (default) = the form of
+                           * the levels above it (mid_form). */
     int nu_inc;           /* variable V-cycle (V_var, Sec. 5): level l runs
                            * nu1 + nu_inc (L - l) pre- and nu2 + nu_inc (L - l)
                            * post-smoothing steps, L the finest level;
                            * 0 (default) = the same count on every level. */
+    int mid_form;         /* viscous form of the levels strictly between the
+                           * finest and the coarsest inside V-cycles: -1
+                           * (default) = the form of the call (Sec. 5 keeps
+                           * the stencil form on the finer grids). */
+    int merge_max_n;      /* kernel shapes of the smoother (results are the
+                           * same for every setting): levels with n <=
+                           * merge_max_n cells per axis launch each colour
+                           * phase as one merged grid of bulk and special
+                           * rows, larger levels launch bulk and special
+                           * rows separately with the grouped pressure
+                           * right-hand-side pass.  Default 64; 0 selects
+                           * the large-level kernels on every level. */
+    int spec_wide_min;    /* pressure special-row colour lists longer than
+                           * this run in 256-thread workgroups, shorter ones
+                           * in one-wave workgroups.  Default 65536. */
 } iss_options;
 
 typedef struct {
@@ -276,6 +295,26 @@ int iss_adam_step(int64_t n, float* w, float* m, float* v, const float* g, float
  * the preconditioner is z = V(r) + c, c = the band correction computed from
  * r - K V(r), kept only if it lowers that residual's norm. */
 int iss_problem_set_net(iss_problem* p, iss_net* net);
+
+/* Kernel launches of the smoother, counted per kernel shape on the host
+ * at launch time (graph replays of the coarse V-cycle are not counted).
+ * Lets a caller confirm which kernel family served a smoothing call. */
+enum iss_launch_kind {
+    ISS_L_VEL_RHS = 0,        /* g = f - B^T p, all interior rows          */
+    ISS_L_GS_VEL_BULK,        /* velocity colour phase, bulk rows          */
+    ISS_L_GS_VEL_SPECIAL,     /* velocity colour phase, special rows       */
+    ISS_L_GS_VEL_MERGED,      /* velocity colour phase, bulk + special     */
+    ISS_L_P_RHS_GROUPED,      /* s = B u - C p - g, grouped (large levels) */
+    ISS_L_P_RHS_MERGED,       /* s pass merged with colour-0 special rows  */
+    ISS_L_GS_P_BULK,          /* pressure colour phase, bulk rows          */
+    ISS_L_GS_P_SPECIAL,       /* pressure special rows, one-wave groups    */
+    ISS_L_GS_P_SPECIAL_WIDE,  /* pressure special rows, 256-thread groups  */
+    ISS_L_GS_P_MERGED,        /* pressure colour phase, bulk + special     */
+    ISS_L_KINDS
+};
+/* Copy the ISS_L_KINDS counters into counts (host, n >= ISS_L_KINDS
+ * entries); reset != 0 then zeroes them. */
+int iss_launch_counts(iss_problem* p, int64_t* counts, int n, int reset);
 
 /* Message describing the last error on the calling thread. */
 const char* iss_last_error(void);

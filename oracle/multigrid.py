@@ -4,12 +4,11 @@ Smoothing step (eq. Uzawa_smooth):
     u <- u + A_hat^{-1} (f - A u - B^T p)
     p <- p + S_hat^{-1} (B u - C p - g)
 A_hat is one symmetric Gauss-Seidel sweep on the velocity block; S_hat is
-one forward Gauss-Seidel sweep on C started from zero, scaled by omega = 0.3
-(Sec. 5: "forward variant of the Gauss-Seidel method applied to the
-stabilization matrix C, with omega = 0.3 as under-relaxation factor").
+one forward Gauss-Seidel sweep on the stabilisation block C started from
+zero, damped by the factor omega = 0.3 (Sec. 5, eq. Uzawa_smooth).
 
 Readings taken where Sec. 5 leaves the choice open:
-  * ordering: the paper's "symmetric hybrid parallel row-wise red-black"
+  * ordering: the paper's symmetric, parallel red-black style row-wise
     Gauss-Seidel becomes a global multicolour Gauss-Seidel with colour
     (i + j [+ k]) mod (d + 1); the forward sweep visits colours 0..d and,
     inside a vertex, components 0..d-1; the backward sweep is the exact
@@ -20,7 +19,12 @@ Readings taken where Sec. 5 leaves the choice open:
   * transfers: prolongation is P1 interpolation between nested Kuhn
     lattices, restriction its transpose; velocity entries of Dirichlet
     vertices are zeroed after restriction.
-  * coarse operators: rediscretisation with the centroid rule on each level.
+  * coarse operators: rediscretisation with the centroid rule on each level,
+    or with the volume-averaged fine viscosity (Galerkin for nested P1).
+  * forms per level: the finest level uses the form of the call; the levels
+    in between use ``mid_form`` (default: the same form); the coarsest uses
+    ``coarse_form`` (default: that of the levels above), which expresses the
+    swap to the strain form on the coarse grid of Sec. 5.
   * coarse solve: direct, on the free dofs bordered by the pressure
     constraint sum_j w_j p_j = 0 (a direct coarse solver is the case the
     paper calls unproblematic, Sec. 5).
@@ -96,18 +100,22 @@ def parent_elements(dim, n_coarse):
     return parent
 
 
-def averaged_coarse_viscosity(dim, n_coarse, mu_f, imu_f, pure_values, nbins=250):
+def averaged_coarse_viscosity(dim, n_coarse, mu_f, imu_f, pure_values, table=None, nbins=250):
     """Coarse-element viscosity as the volume average over the nested fine
     elements (equal volumes under uniform refinement), and the same for
     1/mu.  For nested P1 spaces the viscous block assembled with these
     averages equals the Galerkin product P^T A P.
 
-    Reading taken for the per-level representation: averages equal to a
-    viscosity of the problem (pure elements) are kept exactly; the other
-    averages are grouped into ``nbins`` logarithmically spaced bins between
-    the smallest and largest mixed average of the level, and every member
-    of a bin takes the bin's mean of mu and of 1/mu.
-    Returns the unbinned averages (mu, 1/mu) and the binned ones."""
+    Returns the averages (mu, 1/mu) and their representation on the level.
+    With ``table=None`` (the definition) the representation is the averages
+    themselves.  With a table size, it models a level that stores at most
+    ``table`` distinct viscosities: averages equal to a viscosity of the
+    problem (pure elements) are kept exactly, the distinct mixed averages
+    are kept exactly if they fit the table, and otherwise they are grouped
+    into ``nbins`` logarithmically spaced bins between the smallest and
+    largest mixed average, every member of a bin taking the bin's mean of mu
+    and of 1/mu.  This approximation is used only to bound its effect on the
+    V-cycle (a test), never as the reference."""
     parent = parent_elements(dim, n_coarse)
     nce = n_coarse ** dim * (6 if dim == 3 else 2)
     kids = np.bincount(parent, minlength=nce)
@@ -115,11 +123,16 @@ def averaged_coarse_viscosity(dim, n_coarse, mu_f, imu_f, pure_values, nbins=250
     imu_avg = np.bincount(parent, imu_f, minlength=nce) / kids
     pure = np.zeros(nce, dtype=bool)
     mu_q, imu_q = mu_avg.copy(), imu_avg.copy()
-    for v in pure_values:
+    if table is None:
+        return mu_avg, imu_avg, mu_q, imu_q
+    npure = 0
+    for v in sorted(set(pure_values)):
         hit = (np.abs(mu_avg - v) <= 1e-14 * v) & (np.abs(imu_avg * v - 1.0) < 1e-12)
+        npure += bool(hit.any())
         pure |= hit
         mu_q[hit], imu_q[hit] = v, 1.0 / v
-    if (~pure).any():
+    nmixed = len(set(zip(mu_avg[~pure].tolist(), imu_avg[~pure].tolist())))
+    if (~pure).any() and npure + nmixed > table:
         lm = np.log(mu_avg[~pure])
         lo, hi = lm.min(), lm.max()
         t = (lm - lo) / (hi - lo) if hi > lo else np.zeros_like(lm)
@@ -212,27 +225,32 @@ class Hierarchy:
     """Levels n_l = m 2^l for l = coarse..fine (m macro cubes per axis)."""
 
     def __init__(self, dim, m, fine_level, coarse_level, inclusions, mu_table, form,
-                 nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None, nu_inc=0):
+                 nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None, nu_inc=0,
+                 mid_form=None, table=None):
         """coarse_mu: 'centroid' rediscretises every level with the centroid
         rule; 'average' uses averaged_coarse_viscosity below the finest
-        level.  coarse_form: viscous form of the levels below the finest
-        (Sec. 5 swaps to the strain form on the coarse grid); default: the
-        same form on every level.  nu_inc: variable V-cycle (V_var of
-        Sec. 5), nu_inc more pre- and post-smoothing steps per level below
-        the finest."""
+        level (``table``: its table-size model, None = exact averages).
+        mid_form: viscous form of the levels strictly between the finest and
+        the coarsest (default: ``form``).  coarse_form: viscous form of the
+        coarsest level (Sec. 5 swaps to the strain form on the coarse grid;
+        default: the form of the levels above).  nu_inc: variable V-cycle
+        (V_var of Sec. 5), nu_inc more pre- and post-smoothing steps per
+        level below the finest."""
         self.dim = dim
         self.levels = {}
         self.P = {}
-        cform = form if coarse_form is None else coarse_form
+        mform = form if mid_form is None else mid_form
+        cform = mform if coarse_form is None else coarse_form
         mu_f = imu_f = None
         for l in range(fine_level, coarse_level - 1, -1):
             n = m * 2 ** l
-            f = form if l == fine_level else cform
+            f = form if l == fine_level else (cform if l == coarse_level else mform)
             if l == fine_level or coarse_mu == 'centroid':
                 self.levels[l] = Level(dim, n, inclusions, mu_table, f)
                 mu_f, imu_f = self.levels[l].disc.mu_e, self.levels[l].disc.imu_e
             else:
-                mu_f, imu_f, mq, iq = averaged_coarse_viscosity(dim, n, mu_f, imu_f, list(mu_table))
+                mu_f, imu_f, mq, iq = averaged_coarse_viscosity(dim, n, mu_f, imu_f, list(mu_table),
+                                                                table=table)
                 self.levels[l] = Level(dim, n, inclusions, mu_table, f, mu_e=mq, imu_e=iq)
             if l > coarse_level:
                 self.P[l] = prolongation(dim, m * 2 ** (l - 1))

@@ -33,7 +33,13 @@ class Inclusion(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int),
-                ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int)]
+                ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int),
+                ("mid_form", ctypes.c_int), ("merge_max_n", ctypes.c_int), ("spec_wide_min", ctypes.c_int)]
+
+
+# iss_launch_kind: smoother kernel shapes counted by iss_launch_counts
+LAUNCH_KINDS = ["vel_rhs", "gs_vel_bulk", "gs_vel_special", "gs_vel_merged", "p_rhs_grouped",
+                "p_rhs_merged", "gs_p_bulk", "gs_p_special", "gs_p_special_wide", "gs_p_merged"]
 
 
 class SolveInfo(ctypes.Structure):
@@ -49,7 +55,7 @@ EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "
            "iss_dot", "iss_last_error", "iss_net_create", "iss_net_destroy", "iss_net_info",
            "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
            "iss_net_targets", "iss_net_backward", "iss_adam_step", "iss_problem_set_net",
-           "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed"]
+           "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed", "iss_launch_counts"]
 
 
 def lib():
@@ -99,6 +105,7 @@ def lib():
     L.iss_problem_set_net.argtypes = [vp, vp]
     L.iss_net_correction.argtypes = [vp, vp, vp]
     L.iss_net_output_grad.argtypes = [vp, vp, cdbl, vp]
+    L.iss_launch_counts.argtypes = [vp, ctypes.POINTER(i64), cint, cint]
     _lib = L
     return L
 
@@ -144,11 +151,12 @@ class Problem:
 
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
-                 coarse_form=None, nu_inc=0):
+                 coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
-                      -1 if coarse_form is None else FORMS[coarse_form], nu_inc)
+                      -1 if coarse_form is None else FORMS[coarse_form], nu_inc,
+                      -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min)
         incs = inclusions_to_c(inclusions)
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()
@@ -273,6 +281,13 @@ class Problem:
         return {"status": rc, "iterations": info.iterations, "relres": info.relres,
                 "seconds": info.seconds, "history": [hist[i] for i in range(info.history_len)],
                 "net_accepted": info.net_accepted, "net_rejected": info.net_rejected}
+
+    def launch_counts(self, reset=False):
+        """Smoother kernel launches per kernel shape since creation (or the
+        last reset), as a dict keyed by LAUNCH_KINDS."""
+        c = (ctypes.c_int64 * len(LAUNCH_KINDS))()
+        _check(lib().iss_launch_counts(self._h, c, len(LAUNCH_KINDS), int(reset)))
+        return dict(zip(LAUNCH_KINDS, list(c)))
 
     def dot(self, a, b):
         import torch

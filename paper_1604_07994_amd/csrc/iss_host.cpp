@@ -203,7 +203,8 @@ struct Coarse {
 
 }  // namespace
 
-// the part of a V-cycle below the finest level, recorded once as a HIP graph
+// the part of a V-cycle below the finest level (for one form of the call on
+// the finest level), recorded once as a HIP graph
 struct VGraph {
     bool warm = false;              // one eager run done (buffers and coarse inverse exist)
     hipGraphExec_t exec = nullptr;
@@ -242,6 +243,7 @@ struct iss_problem {
     bool use_graphs = true;
     VGraph vgraph[3][3];
     hipStream_t cap_stream = nullptr;
+    int64_t launch_count[ISS_L_KINDS] = {};   // smoother launches per kernel shape
     std::vector<void*> allocs;
 };
 
@@ -384,9 +386,10 @@ void averaged_viscosity(iss_problem* p, int l) {
     }
     std::vector<double>().swap(F.emu);
     std::vector<double>().swap(F.eimu);
-    // phases: one per distinct pure viscosity of the problem, then at most
-    // 250 logarithmic bins of the mixed averages (relative width < 2% for
-    // contrasts up to 1e4; each bin stores the mean of its members)
+    // phases: one per distinct pure viscosity of the problem, then one per
+    // distinct mixed average when they all fit the 254-entry table, else at
+    // most 250 logarithmic bins of the mixed averages (each bin stores the
+    // mean of its members; relative width below 4% for contrasts up to 1e4)
     std::vector<double> tab_mu, tab_imu;
     std::vector<double> sum_mu(256, 0.0), sum_imu(256, 0.0), cnt(256, 0.0);
     double lo = 1e300, hi = -1e300;
@@ -411,14 +414,28 @@ void averaged_viscosity(iss_problem* p, int l) {
         if (!pure) { lo = std::min(lo, std::log(m)); hi = std::max(hi, std::log(m)); }
     }
     const int npure = (int)pure_vals.size();
-    const int nbins = std::max(1, std::min(250, 254 - npure));
+    // the distinct mixed averages, kept exactly when they fit the table
+    std::vector<std::pair<double, double>> mixed;
+    for (int64_t e = 0; e < ne; ++e) {
+        const double m = L.emu[e], im = L.eimu[e];
+        bool pure = false;
+        for (int q = 0; q < npure && !pure; ++q)
+            pure = std::fabs(m - pure_vals[q]) <= 1e-14 * pure_vals[q] && std::fabs(im * pure_vals[q] - 1.0) < 1e-12;
+        if (!pure) mixed.emplace_back(m, im);
+    }
+    std::sort(mixed.begin(), mixed.end());
+    mixed.erase(std::unique(mixed.begin(), mixed.end()), mixed.end());
+    const bool exact = npure + (int64_t)mixed.size() <= 254;
+    const int nbins = exact ? (int)mixed.size() : std::max(1, std::min(250, 254 - npure));
     std::vector<int> bin_of_elem(ne, -1);
     for (int64_t e = 0; e < ne; ++e) {
         const double m = L.emu[e], im = L.eimu[e];
         int k = -1;
         for (int q = 0; q < npure; ++q)
             if (std::fabs(m - pure_vals[q]) <= 1e-14 * pure_vals[q] && std::fabs(im * pure_vals[q] - 1.0) < 1e-12) k = q;
-        if (k < 0) {
+        if (k < 0 && exact) {
+            k = npure + (int)(std::lower_bound(mixed.begin(), mixed.end(), std::make_pair(m, im)) - mixed.begin());
+        } else if (k < 0) {
             const double t = (hi > lo) ? (std::log(m) - lo) / (hi - lo) : 0.0;
             k = npure + std::min(nbins - 1, (int)(t * nbins));
         }
@@ -434,8 +451,16 @@ void averaged_viscosity(iss_problem* p, int l) {
     for (int k = 0; k < npure + nbins; ++k) {
         if (cnt[k] == 0) continue;
         remap[k] = nph;
-        L.mu_tab[nph] = (k < npure) ? pure_vals[k] : sum_mu[k] / cnt[k];
-        L.imu_tab[nph] = (k < npure) ? 1.0 / pure_vals[k] : sum_imu[k] / cnt[k];
+        if (k < npure) {
+            L.mu_tab[nph] = pure_vals[k];
+            L.imu_tab[nph] = 1.0 / pure_vals[k];
+        } else if (exact) {
+            L.mu_tab[nph] = mixed[k - npure].first;
+            L.imu_tab[nph] = mixed[k - npure].second;
+        } else {
+            L.mu_tab[nph] = sum_mu[k] / cnt[k];
+            L.imu_tab[nph] = sum_imu[k] / cnt[k];
+        }
         ++nph;
     }
     for (int64_t e = 0; e < ne; ++e) L.elem_phase[e] = (uint8_t)remap[bin_of_elem[e]];
@@ -564,6 +589,9 @@ int setup_level(iss_problem* p, int l) {
     V.Pp = Pp;
     V.Ns = Ns;
     V.vphase_s = L.d_vphase_s;
+    V.merge_max_n = p->opt.merge_max_n;
+    V.spec_wide_min = p->opt.spec_wide_min;
+    V.launch_count = p->launch_count;
     return ISS_OK;
 }
 
@@ -747,6 +775,17 @@ int check_level(const iss_problem* p, int l) {
     return (l >= p->coarse && l <= p->levels) ? ISS_OK : fail(ISS_E_INVAL, "level out of range");
 }
 
+// Viscous form of level l inside a V-cycle called with `form` on the finest
+// level: the finest level keeps the call's form, the levels in between take
+// mid_form (default: the call's form), the coarsest takes coarse_form
+// (default: that of the levels above it).
+int level_form(const iss_problem* p, int l, int form) {
+    if (l == p->levels) return form;
+    const int mid = p->opt.mid_form >= 0 ? p->opt.mid_form : form;
+    if (l == p->coarse) return p->opt.coarse_form >= 0 ? p->opt.coarse_form : mid;
+    return mid;
+}
+
 int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hipStream_t s) {
     int rc;
     if ((rc = ensure_coarse(p, form))) return rc;
@@ -760,9 +799,10 @@ int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hip
     return ISS_OK;
 }
 
-// V(nu1, nu2) cycle on level l.  x_zero: x holds zero on entry (it is then
-// not read).  Smoothing runs on colour-split copies of x and b; b is packed
-// once for both smoothing phases.
+// V(nu1, nu2) cycle on level l for a cycle called with `form` on the finest
+// level (each level uses level_form).  x_zero: x holds zero on entry (it is
+// then not read).  Smoothing runs on colour-split copies of x and b; b is
+// packed once for both smoothing phases.
 int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bool x_zero, hipStream_t s);
 
 // The V-cycle below the finest level touches only the library's per-level
@@ -806,7 +846,8 @@ int coarse_part(iss_problem* p, int l, int form, int prec, hipStream_t s, bool t
 }
 
 int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bool x_zero, hipStream_t s) {
-    if (l == p->coarse) return coarse_solve(p, form, prec, b, x, s);
+    if (l == p->coarse) return coarse_solve(p, level_form(p, l, form), prec, b, x, s);
+    const int lform = level_form(p, l, form);
     int rc;
     if ((rc = ensure_work(p, l, prec)) || (rc = ensure_work(p, l - 1, prec))) return rc;
     Level& L = p->lv[l];
@@ -820,17 +861,16 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bo
     const int extra = p->opt.nu_inc * (p->levels - l);      // V_var: more steps on coarser levels
     const int nu1 = p->opt.nu1 + extra, nu2 = p->opt.nu2 + extra;
     for (int i = 0; i < nu1; ++i)
-        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s));
+        ISS_HIP(k_smooth_step(L.v, lform, prec, p->opt.omega, xs, bs, ws, i == 0, s));
     ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
-    ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
+    ISS_HIP(k_apply(L.v, lform, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
     ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
-    const int cform = (p->opt.coarse_form >= 0) ? p->opt.coarse_form : form;
-    if ((rc = coarse_part(p, l - 1, cform, prec, s, l == p->levels))) return rc;
+    if ((rc = coarse_part(p, l - 1, form, prec, s, l == p->levels))) return rc;
     ISS_HIP(k_prolong_add(L.v, Lc.v, prec, Lc.w_x[prec], x, s));
     if (nu2 > 0) {
         ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
         for (int i = 0; i < nu2; ++i)
-            ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s));
+            ISS_HIP(k_smooth_step(L.v, lform, prec, p->opt.omega, xs, bs, ws, i == 0, s));
         ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
     }
     return ISS_OK;
@@ -920,7 +960,7 @@ int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
     const int m = std::max(1, p->opt.restart);
     int rc;
     if ((rc = ensure_krylov(p, m))) return rc;
-    if ((rc = ensure_coarse(p, (p->levels > p->coarse && p->opt.coarse_form >= 0) ? p->opt.coarse_form : form))) return rc;
+    if ((rc = ensure_coarse(p, level_form(p, p->coarse, form)))) return rc;
     double sq[4];
     if ((rc = field_norms(p, PREC_F64, b, N, D + 1, sq, s))) return rc;
     const double nb = total_norm(sq, D + 1);
@@ -1107,6 +1147,9 @@ int iss_default_options(iss_options* o) {
     o->coarse_mu = ISS_COARSE_MU_AVERAGE;
     o->coarse_form = -1;
     o->nu_inc = 0;
+    o->mid_form = -1;
+    o->merge_max_n = 64;
+    o->spec_wide_min = 65536;
     return ISS_OK;
 }
 
@@ -1133,6 +1176,14 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     const int64_t n = (int64_t)macro << levels;
     const int64_t N = (dim == 3) ? (n + 1) * (n + 1) * (n + 1) : (n + 1) * (n + 1);
     if ((int64_t)(dim + 1) * N >= (int64_t)1 << 31) return fail(ISS_E_INVAL, "problem too large for int32 indices");
+    {
+        // the smoother addresses a split-layout field through 32-bit byte
+        // offsets: every FP64 field must stay below 4 GiB
+        const int64_t q = (n + 1 + dim) / (dim + 1);
+        const int64_t Ns = (int64_t)(dim + 1) * q * (dim == 3 ? (n + 1) * (n + 1) : (n + 1));
+        if (Ns * (int64_t)sizeof(double) >= (int64_t)1 << 32)
+            return fail(ISS_E_INVAL, "problem too large: a split-layout field exceeds 4 GiB");
+    }
     if (!mu || nphase < 1 || nphase > 254) return fail(ISS_E_INVAL, "need 1 <= nphase <= 254");
     for (int i = 0; i < nphase; ++i)
         if (!(mu[i] > 0) || !std::isfinite(mu[i])) return fail(ISS_E_INVAL, "viscosities must be positive and finite");
@@ -1162,7 +1213,8 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     if (p->opt.nu1 < 0 || p->opt.nu2 < 0 || p->opt.nu_inc < 0 || !(p->opt.stab_beta > 0) || p->opt.restart < 1 ||
         (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES) ||
         (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
-        p->opt.coarse_form < -1 || p->opt.coarse_form > 2) {
+        p->opt.coarse_form < -1 || p->opt.coarse_form > 2 || p->opt.mid_form < -1 || p->opt.mid_form > 2 ||
+        p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }
@@ -1414,6 +1466,14 @@ int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double*
     ISS_HIP(hipMemcpyAsync(p->h_pinned, p->d_red, sizeof(double), hipMemcpyDeviceToHost, s));
     ISS_HIP(hipStreamSynchronize(s));
     *out = p->h_pinned[0];
+    return ISS_OK;
+}
+
+int iss_launch_counts(iss_problem* p, int64_t* counts, int n, int reset) {
+    if (!p || !counts || n < ISS_L_KINDS) return fail(ISS_E_INVAL, "need a problem and ISS_L_KINDS counters");
+    for (int k = 0; k < ISS_L_KINDS; ++k) counts[k] = p->launch_count[k];
+    if (reset)
+        for (int k = 0; k < ISS_L_KINDS; ++k) p->launch_count[k] = 0;
     return ISS_OK;
 }
 

@@ -40,6 +40,11 @@ struct LevelView {
     int q, Rp;
     int64_t Pp, Ns;
     const uint8_t* vphase_s; // phase bytes in the split layout (padding SPECIAL)
+    // smoother launch shapes (host side): merged colour phases up to this n,
+    // 256-thread pressure special groups above this list length
+    int merge_max_n;
+    int64_t spec_wide_min;
+    int64_t* launch_count;   // host counters per iss_launch_kind, or null
 };
 
 enum { SPLIT_PACK = 0, SPLIT_UNPACK = 1 };

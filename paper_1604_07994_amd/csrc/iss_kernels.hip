@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "iss.h"
 #include "iss_internal.h"
 
 namespace iss {
@@ -1057,7 +1058,6 @@ __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour
 // work; long lists keep 4-wave groups (neighbouring boundary rows share a
 // CU's L1), short ones use one wave per group to reach more CUs.
 constexpr int SPEC_WG = 64;
-constexpr int64_t SPEC_P_LONG = 65536;   // pressure special rows per colour above which 4-wave groups are used
 template <int D, int F, bool BWD, typename T>
 __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
                                                   const T* __restrict__ g) {
@@ -1602,8 +1602,10 @@ hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, 
 
 static inline unsigned blocks256(int64_t threads) { return (unsigned)((threads + 255) / 256); }
 
-// levels up to this size run each colour phase as one merged launch
-constexpr int MERGE_MAX_N = 64;
+// host-side launch counter of the smoother kernels (iss_launch_counts)
+static inline void counted(const LevelView& L, int kind) {
+    if (L.launch_count) ++L.launch_count[kind];
+}
 
 // One Uzawa step (eq. Uzawa_smooth) on split-layout vectors: symmetric
 // velocity sweep (forward colours 0..d, backward d..0; bulk then special
@@ -1623,9 +1625,11 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
     T* g = ws;
     T* sres = ws;
     T* delta = ws + (int64_t)D * L.Ns;
-    const bool merge = L.n <= MERGE_MAX_N;       // one launch per colour phase
-    if (ba > 0)
+    const bool merge = L.n <= L.merge_max_n;     // one launch per colour phase
+    if (ba > 0) {
         hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, g);
+        counted(L, ISS_L_VEL_RHS);
+    }
     for (int pass = 0; pass < 2; ++pass) {
         for (int cc = 0; cc <= D; ++cc) {
             const int c = pass == 0 ? cc : D - cc;
@@ -1639,19 +1643,26 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                 else
                     hipLaunchKernelGGL((k_gs_vel_m<D, F, true, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c,
                                        xs, g, bs, bc);
+                counted(L, ISS_L_GS_VEL_MERGED);
                 if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
-            } else if (pass == 0) {
-                if (bc > 0)
-                    hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
-                if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
-                if (ns > 0)
-                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L, c, xs, bs);
             } else {
-                if (bc > 0)
-                    hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
+                if (bc > 0) {
+                    if (pass == 0)
+                        hipLaunchKernelGGL((k_gs_vel_s<D, F, false, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
+                    else
+                        hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
+                    counted(L, ISS_L_GS_VEL_BULK);
+                }
                 if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
-                if (ns > 0)
-                    hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L, c, xs, bs);
+                if (ns > 0) {
+                    if (pass == 0)
+                        hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L,
+                                           c, xs, bs);
+                    else
+                        hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L,
+                                           c, xs, bs);
+                    counted(L, ISS_L_GS_VEL_SPECIAL);
+                }
             }
         }
     }
@@ -1666,22 +1677,30 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             if (merge && nb + ns > 0) {
                 hipLaunchKernelGGL((k_p_rhs_s<D, T>), dim3((unsigned)(4 * nb + nsw)), dim3(64), 0, s, L, xs, bs,
                                    sres, delta, nb);
+                counted(L, ISS_L_P_RHS_MERGED);
                 continue;
             }
-            if (ba > 0)
+            if (ba > 0) {
                 hipLaunchKernelGGL((k_p_rhs_g<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, sres, delta);
+                counted(L, ISS_L_P_RHS_GROUPED);
+            }
         } else if (merge && bc > 0 && ns > 0) {
             hipLaunchKernelGGL((k_gs_p_m<D, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c, sres, xs, bs,
                                delta, bc);
+            counted(L, ISS_L_GS_P_MERGED);
             continue;
         } else if (bc > 0) {
             hipLaunchKernelGGL((k_gs_p_s<D, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, sres, delta);
+            counted(L, ISS_L_GS_P_BULK);
         }
-        if (ns > 0 && L.spec_off[c + 1] - L.spec_off[c] > SPEC_P_LONG)
+        if (ns > 0 && L.spec_off[c + 1] - L.spec_off[c] > L.spec_wide_min) {
             hipLaunchKernelGGL((k_gs_p_special_s<D, T, 256>), dim3((unsigned)ns), dim3(256), 0, s, L, c, xs, bs, delta);
-        else if (ns > 0)
+            counted(L, ISS_L_GS_P_SPECIAL_WIDE);
+        } else if (ns > 0) {
             hipLaunchKernelGGL((k_gs_p_special_s<D, T, SPEC_WG>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L, c, xs,
                                bs, delta);
+            counted(L, ISS_L_GS_P_SPECIAL);
+        }
     }
     hipLaunchKernelGGL((k_axpy_clear<T>), grid1(L.Ns), dim3(256), 0, s, xs + (int64_t)D * L.Ns, delta,
                        (typename Acc<T>::type)omega, L.Ns);

@@ -46,6 +46,8 @@ def test_argument_validation_without_gpu():
     opt = binding.Options()
     assert L.iss_default_options(ctypes.byref(opt)) == 0
     assert opt.nu1 == 3 and opt.nu2 == 3 and abs(opt.omega - 0.3) < 1e-15
+    assert opt.coarse_form == -1 and opt.mid_form == -1
+    assert opt.merge_max_n == 64 and opt.spec_wide_min == 65536
 
 
 def _create(L, binding, dim=3, macro=1, levels=2, coarse=1, incs=(), mu=(1.0,), opt=None):
@@ -78,8 +80,20 @@ def test_problem_create_rejects_bad_arguments(kw, msg):
     assert rc == -1 and msg in err, (rc, err)
 
 
+def test_problem_create_rejects_split_field_beyond_4gib():
+    """A 2D lattice that passes the int32 index bound but whose colour-split
+    smoother field would exceed 4 GiB (32-bit byte offsets) is rejected
+    before any device call: macro 3, 13 refinements (24577^2 vertices)."""
+    from paper_1604_07994_amd import binding
+    L = binding.lib()
+    rc, err = _create(L, binding, dim=2, macro=3, levels=13, coarse=3)
+    assert rc == -1 and "4 GiB" in err, (rc, err)
+
+
 @pytest.mark.parametrize("field,value", [("nu1", -1), ("nu_inc", -2), ("restart", 0), ("outer", 5),
-                                         ("coarse_mu", 7), ("coarse_form", 3), ("stab_beta", 0.0)])
+                                         ("coarse_mu", 7), ("coarse_form", 3), ("stab_beta", 0.0),
+                                         ("mid_form", -2), ("mid_form", 3), ("merge_max_n", -1),
+                                         ("spec_wide_min", -1)])
 def test_problem_create_rejects_bad_options(field, value):
     from paper_1604_07994_amd import binding
     L = binding.lib()

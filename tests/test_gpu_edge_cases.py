@@ -109,6 +109,30 @@ def test_smoother_step_parity(case, form):
     assert err < 1e-11, (name, form, err)
 
 
+@pytest.mark.parametrize("form", ["strain", "interface"])
+@pytest.mark.parametrize("path", [dict(merge_max_n=0), dict(merge_max_n=0, spec_wide_min=0)],
+                         ids=["large", "large-wide"])
+def test_smoother_step_parity_large_path(case, form, path):
+    """The same step through the kernels of the levels above 65^3 (separate
+    bulk and special launches, grouped pressure pass, one-wave or 256-thread
+    pressure special groups)."""
+    name, w, _, D = case
+    P = gpu_problem(w, **path)
+    lv = mg.Level(w["dim"], w["n"], w["inclusions"], w["mu"], form)
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=46)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=47)
+    xg = to_dev(x)
+    P.launch_counts(reset=True)
+    P.smooth(form, xg, to_dev(b), nsteps=2)
+    c = P.launch_counts()
+    assert c["gs_vel_merged"] == c["p_rhs_merged"] == c["gs_p_merged"] == 0, c
+    assert c["p_rhs_grouped"] == 2, c
+    ref = mg.smooth(lv, x, b, 2)
+    err = np.abs(to_host(xg) - ref).max() / max(np.abs(ref).max(), 1e-300)
+    assert err < 1e-11, (name, form, err)
+    P.close()
+
+
 def test_zero_input_gives_zero(case):
     import torch
     name, w, P, D = case

@@ -56,7 +56,8 @@ def test_graph_solve_matches_eager():
     and solution with and without the recorded coarse cycle."""
     import torch
     w = small_workload("sinker_3d", 4)
-    kw = dict(outer="fgmres", coarse_mu="average", coarse_form="strain", nu_inc=2, omega=0.6)
+    kw = dict(outer="fgmres", coarse_mu="average", coarse_form="strain", mid_form="strain", nu_inc=2,
+              omega=0.6)
     b = to_dev(iss_inputs.random_rhs(3, w["n"], seed=70))
     out = []
     for graphs in (False, True):

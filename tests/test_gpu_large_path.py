@@ -1,0 +1,155 @@
+"""GPU parity of the smoother kernels that serve the levels above 65^3.
+
+On levels with n > 64 (129^3 and 257^3 in the benchmark) the Uzawa step of
+eq. Uzawa_smooth runs in separate bulk and special launches per colour
+phase: k_vel_rhs_s, k_gs_vel_s, k_gs_vel_special_s, the grouped pressure
+right-hand-side pass k_p_rhs_g (which also finishes colour 0), k_gs_p_s and
+k_gs_p_special_s in one-wave or 256-thread workgroups.  Smaller levels use
+merged launches.  The option merge_max_n = 0 selects the large-level
+kernels on every level and spec_wide_min = 0 sends every pressure special
+list to the 256-thread kernel, so these kernels are compared with the
+oracle here at sizes the oracle handles (17^3 to 33^3, 33^2, a ragged
+25^3), and the host launch counters show which kernels ran.
+
+Tolerances: FP64 as for the merged path (one smoothing step 1e-11, one
+V-cycle 1e-10, relative to max |x|).  FP32 (vectors and arithmetic in
+FP32): each updated entry is a short sum of products rounded at u = 2^-24
+~ 6e-8, and a Gauss-Seidel step carries earlier updates forward; one step
+is held to 1e-5 (~170 u) of max |x| against the FP64 oracle run on the
+same FP32-rounded input, one V-cycle to 1e-4."""
+import itertools
+
+import numpy as np
+import pytest
+
+import iss_inputs
+from oracle import multigrid as mg
+from tests.gpu_common import gpu_problem, small_workload, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("square_split_2d", 5, None), ("sphere_3d", 4, None), ("sinker_3d", 4, None),
+         ("sphere_3d", 3, 3)]
+PATHS = {"large": dict(merge_max_n=0), "large-wide": dict(merge_max_n=0, spec_wide_min=0)}
+PARAMS = list(itertools.product(CASES, sorted(PATHS)))
+
+
+@pytest.fixture(scope="module", params=PARAMS,
+                ids=["%s-L%d-m%s-%s" % (c + (p,)) for c, p in PARAMS])
+def case(request):
+    (name, levels, macro), path = request.param
+    w = small_workload(name, levels, macro)
+    w["coarse"] = min(w["coarse"], levels - 1)
+    P = gpu_problem(w, outer="fgmres", **PATHS[path])
+    yield w, P, path
+    P.close()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _check_large_launches(c, d, path, steps):
+    """Launch counts of `steps` smoothing steps on one level through the
+    large-level kernels (every colour list holds boundary vertices, so every
+    special launch is made)."""
+    m = d + 1
+    assert c["gs_vel_merged"] == c["p_rhs_merged"] == c["gs_p_merged"] == 0, c
+    assert c["vel_rhs"] == steps and c["p_rhs_grouped"] == steps, c
+    assert c["gs_vel_bulk"] == 2 * m * steps and c["gs_vel_special"] == 2 * m * steps, c
+    assert c["gs_p_bulk"] == d * steps, c
+    if path == "large-wide":
+        assert c["gs_p_special_wide"] == m * steps and c["gs_p_special"] == 0, c
+    else:
+        assert c["gs_p_special"] == m * steps and c["gs_p_special_wide"] == 0, c
+
+
+@pytest.mark.parametrize("form", ["gradient", "strain", "interface"])
+def test_smoother_steps_large_path(case, form):
+    w, P, path = case
+    lv = mg.Level(w["dim"], w["n"], w["inclusions"], w["mu"], form)
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=121)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=122)
+    xg = to_dev(x)
+    P.launch_counts(reset=True)
+    P.smooth(form, xg, to_dev(b), nsteps=2)
+    _check_large_launches(P.launch_counts(), w["dim"], path, 2)
+    ref = mg.smooth(lv, x, b, 2)
+    assert _rel(to_host(xg), ref) < 1e-11, form
+
+
+@pytest.mark.parametrize("form", ["strain", "interface"])
+def test_smoother_step_fp32_large_path(case, form):
+    import torch
+    w, P, path = case
+    lv = mg.Level(w["dim"], w["n"], w["inclusions"], w["mu"], form)
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=123).astype(np.float32).astype(np.float64)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=124).astype(np.float32).astype(np.float64)
+    xg = to_dev(x, torch.float32)
+    P.launch_counts(reset=True)
+    P.smooth(form, xg, to_dev(b, torch.float32), nsteps=1)
+    _check_large_launches(P.launch_counts(), w["dim"], path, 1)
+    ref = mg.smooth(lv, x, b, 1)
+    assert _rel(to_host(xg), ref) < 1e-5, form
+
+
+@pytest.mark.parametrize("form", ["gradient", "strain", "interface"])
+def test_vcycle_large_path(case, form):
+    w, P, path = case
+    H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"], form)
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=128)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=129)
+    xg = to_dev(x)
+    P.launch_counts(reset=True)
+    P.vcycle(form, xg, to_dev(b))
+    c = P.launch_counts()
+    assert c["gs_vel_bulk"] > 0 and c["gs_vel_merged"] == 0 and c["p_rhs_merged"] == 0, c
+    ref = H.vcycle(w["levels"], x, b)
+    assert _rel(to_host(xg), ref) < 1e-10, form
+
+
+def test_vcycle_fp32_large_path(case):
+    import torch
+    w, P, path = case
+    H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"], "interface")
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=130).astype(np.float32).astype(np.float64)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=131).astype(np.float32).astype(np.float64)
+    xg = to_dev(x, torch.float32)
+    P.vcycle("interface", xg, to_dev(b, torch.float32))
+    ref = H.vcycle(w["levels"], x, b)
+    assert _rel(to_host(xg), ref) < 1e-4
+
+
+@pytest.mark.parametrize("mid", [None, "strain"])
+@pytest.mark.parametrize("name,levels", [("sphere_3d", 4), ("sinker_3d", 4)])
+def test_vcycle_default_configuration_large_path(name, levels, mid):
+    """The benchmark's V-cycle (averaged coarse viscosity, strain form on
+    the coarsest level, optionally on every level below the finest, V(5,5),
+    omega 0.6) through the large-level kernels on every level."""
+    w = small_workload(name, levels)
+    P = gpu_problem(w, coarse_mu="average", coarse_form="strain", mid_form=mid, omega=0.6, nu1=5, nu2=5,
+                    merge_max_n=0, spec_wide_min=0)
+    H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"],
+                     "interface", nu1=5, nu2=5, omega=0.6, coarse_mu="average", coarse_form="strain",
+                     mid_form=mid)
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=132)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=133)
+    xg = to_dev(x)
+    P.vcycle("interface", xg, to_dev(b))
+    ref = H.vcycle(w["levels"], x, b)
+    assert _rel(to_host(xg), ref) < 1e-10
+    P.close()
+
+
+def test_default_path_is_merged_at_small_sizes():
+    """Without the options, levels up to 65^3 take the merged launches."""
+    w = small_workload("sphere_3d", 4)
+    P = gpu_problem(w)
+    x = to_dev(iss_inputs.random_vector(3, w["n"], seed=134))
+    b = to_dev(iss_inputs.random_rhs(3, w["n"], seed=135))
+    P.launch_counts(reset=True)
+    P.smooth("interface", x, b, nsteps=1)
+    c = P.launch_counts()
+    assert c["gs_vel_merged"] == 8 and c["p_rhs_merged"] == 1 and c["gs_p_merged"] == 3, c
+    assert c["gs_vel_bulk"] == c["p_rhs_grouped"] == c["gs_p_bulk"] == 0, c
+    P.close()

@@ -215,15 +215,19 @@ def test_fgmres_2d_odd_length_matches_oracle():
     P.close()
 
 
-@pytest.mark.parametrize("name,levels", [("sphere_3d", 4), ("sinker_3d", 3)])
-def test_vcycle_default_configuration(name, levels):
-    """The benchmark's configuration: averaged (Galerkin) coarse viscosity,
-    strain form on the coarser levels, interface form on the finest;
-    one V(5,5) cycle with omega 0.6 against the oracle hierarchy."""
+@pytest.mark.parametrize("mid", [None, "strain"], ids=["coarsest-swap", "all-coarser-strain"])
+@pytest.mark.parametrize("name,levels", [("sphere_3d", 4), ("sinker_3d", 3), ("sinker_3d", 4)])
+def test_vcycle_default_configuration(name, levels, mid):
+    """The benchmark's configurations: averaged (Galerkin) coarse viscosity,
+    interface form on the finest level, strain form on the coarsest (the
+    swap of Sec. 5) and either the interface form or the strain form on the
+    levels in between; one V(5,5) cycle with omega 0.6 against the oracle
+    hierarchy."""
     w = small_workload(name, levels)
-    P = gpu_problem(w, coarse_mu="average", coarse_form="strain", omega=0.6, nu1=5, nu2=5)
+    P = gpu_problem(w, coarse_mu="average", coarse_form="strain", mid_form=mid, omega=0.6, nu1=5, nu2=5)
     H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"],
-                     "interface", nu1=5, nu2=5, omega=0.6, coarse_mu="average", coarse_form="strain")
+                     "interface", nu1=5, nu2=5, omega=0.6, coarse_mu="average", coarse_form="strain",
+                     mid_form=mid)
     x = iss_inputs.random_vector(w["dim"], w["n"], seed=31)
     b = iss_inputs.random_rhs(w["dim"], w["n"], seed=32)
     xg = to_dev(x)

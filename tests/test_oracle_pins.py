@@ -427,14 +427,106 @@ def test_averaged_coarse_viscosity_is_galerkin(dim):
 
 
 def test_binned_coarse_viscosity_bounds():
-    """Binning keeps pure viscosities exact and moves mixed ones by less
-    than the bin width (log spacing, 250 bins)."""
+    """The table model of averaged_coarse_viscosity: without a table the
+    representation is the averages themselves; with a table too small for
+    the distinct mixed averages, pure viscosities stay exact and mixed ones
+    move by less than the bin width (log spacing, 250 bins); with a table
+    that holds them all, nothing moves."""
     Df = assemble.Discretisation(3, 16, SPHERE, [1.0, 1e4])
-    mu_a, imu_a, mu_q, imu_q = mg.averaged_coarse_viscosity(3, 8, Df.mu_e, Df.imu_e, [1.0, 1e4])
+    mu_a, imu_a, mu_e, imu_e = mg.averaged_coarse_viscosity(3, 8, Df.mu_e, Df.imu_e, [1.0, 1e4])
+    assert np.array_equal(mu_e, mu_a) and np.array_equal(imu_e, imu_a)
     pure = (mu_a == 1.0) | (mu_a == 1e4)
+    nmixed = len(set(zip(mu_a[~pure], imu_a[~pure])))
+    assert nmixed > 4
+    _, _, mu_q, imu_q = mg.averaged_coarse_viscosity(3, 8, Df.mu_e, Df.imu_e, [1.0, 1e4], table=4)
     assert np.array_equal(mu_q[pure], mu_a[pure])
     width = np.log(mu_a[~pure].max() / mu_a[~pure].min()) / 250
     assert np.max(np.abs(np.log(mu_q[~pure] / mu_a[~pure]))) <= width + 1e-12
+    _, _, mu_t, imu_t = mg.averaged_coarse_viscosity(3, 8, Df.mu_e, Df.imu_e, [1.0, 1e4], table=2 + nmixed)
+    assert np.array_equal(mu_t[~pure], mu_a[~pure]) and np.array_equal(imu_t[~pure], imu_a[~pure])
+    # pure elements take the problem's viscosity exactly (the average of
+    # equal 1/mu values may be off by an ulp)
+    assert np.allclose(imu_t[pure] * mu_t[pure], 1.0, rtol=1e-15, atol=0)
+
+
+def test_binned_coarse_viscosity_changes_vcycle_boundedly():
+    """Effect of the 254-entry viscosity table on the V-cycle: on the 64^3
+    sinker (contrast 1e4, averaged coarse viscosity) the two levels below
+    the 16^3 one hold more distinct averages than the table, so they are
+    binned (relative width below 4%).  One V-cycle with the binned coarse
+    levels differs from the one with exact averages by less than 5% of the
+    correction it computes, and both contract the residual of the same
+    right-hand side alike (ratio within 10%)."""
+    import copy
+    w = iss_inputs.workload('sinker_3d', levels=5)
+    kw = dict(nu1=2, nu2=2, omega=0.6, coarse_mu='average', coarse_form='strain')
+    args = (w['dim'], w['macro'], w['levels'], w['coarse'], w['inclusions'], w['mu'], 'interface')
+    He = mg.Hierarchy(*args, **kw)
+    # the same hierarchy with the table model on the coarse levels (the
+    # finest level and the transfers are shared)
+    Hb = copy.copy(He)
+    Hb.levels = dict(He.levels)
+    mu_f, imu_f = He.levels[w['levels']].disc.mu_e, He.levels[w['levels']].disc.imu_e
+    for l in range(w['levels'] - 1, w['coarse'] - 1, -1):
+        n = w['macro'] * 2 ** l
+        mu_f, imu_f, mq, iq = mg.averaged_coarse_viscosity(3, n, mu_f, imu_f, w['mu'], table=254)
+        Hb.levels[l] = mg.Level(3, n, w['inclusions'], w['mu'], He.levels[l].form, mu_e=mq, imu_e=iq)
+    Hb.coarse_solver = mg.CoarseSolver(Hb.levels[w['coarse']])
+    binned = [l for l in range(w['coarse'], w['levels'])
+              if not np.array_equal(Hb.levels[l].disc.mu_e, He.levels[l].disc.mu_e)]
+    assert binned, "the table should force binning on some coarse level"
+    b = iss_inputs.random_rhs(3, w['n'], seed=5)
+    x0 = np.zeros_like(b)
+    xe = He.vcycle(w['levels'], x0, b)
+    xb = Hb.vcycle(w['levels'], x0, b)
+    assert np.linalg.norm(xb - xe) <= 0.05 * np.linalg.norm(xe)
+    lv = He.levels[w['levels']]
+    re = np.linalg.norm(mg.residual(lv, xe, b))
+    rb = np.linalg.norm(mg.residual(lv, xb, b))
+    assert abs(rb / re - 1.0) < 0.1, (re, rb)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 8), (3, 4)])
+def test_incident_elements_by_brute_force(dim, n):
+    """incident_elements (the candidate-cell search behind the sampled rows)
+    returns exactly the lattice elements that contain a sample vertex:
+    compared with a scan of every element; an interior vertex lies in d!
+    2^d / ... = 6 (2D) or 24 (3D) elements (Kuhn lattice incidence)."""
+    E = mesh.kuhn_elements(dim, n)
+    N = mesh.num_vertices(dim, n)
+    verts = np.unique(np.concatenate([[0, N - 1, N // 2], iss_inputs.sample_vertices(dim, n, 12, seed=3)]))
+    got = mesh.incident_elements(dim, n, verts)
+    ref = E[np.isin(E, verts).any(axis=1)]
+    key = lambda A: sorted(map(tuple, np.sort(A, axis=1)))
+    assert key(got) == key(ref)
+    for v in verts:
+        cnt = int((got == v).any(axis=1).sum())
+        assert cnt == int((E == v).any(axis=1).sum())
+        if not mesh.boundary_mask(dim, n)[v]:
+            assert cnt == (6 if dim == 2 else 24)
+
+
+@pytest.mark.parametrize("form", ["gradient", "strain", "interface"])
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_sampled_rows_equal_full_assembly(dim, n, form):
+    """sampled_stokes_rows (the oracle of the full-size sampled parity tests)
+    equals the rows of the globally assembled, Dirichlet-masked K x at
+    boundary, interface and bulk vertices, for every form."""
+    inc = SPLIT if dim == 2 else iss_inputs.workload('sinker_3d', levels=2)['inclusions']
+    mu = [1.0, 300.0]
+    D = assemble.Discretisation(dim, n, inc, mu)
+    x = iss_inputs.random_vector(dim, n, seed=7)
+    y = D.stokes(form) @ x
+    bnd = np.nonzero(D.boundary)[0]
+    itf = np.nonzero(D.interface & ~D.boundary)[0]
+    blk = np.nonzero(~D.interface & ~D.boundary)[0]
+    assert len(itf) > 0
+    verts = np.unique(np.concatenate([bnd[::7], itf[::3], blk[::11]]))
+    vs, Y = assemble.sampled_stokes_rows(dim, n, inc, mu, verts, form, x)
+    N = D.N
+    ref = np.stack([y[f * N + vs] for f in range(dim + 1)])
+    scale = np.abs(ref).max()
+    assert np.abs(Y - ref).max() <= 1e-13 * scale
 
 
 def test_interface_form_inertia():
