@@ -186,7 +186,10 @@ int iss_residual(iss_problem* p, int form, int level, int prec, const void* x,
  * right-hand side b: symmetric multicolour Gauss-Seidel on the velocity
  * (colours (i+j+k) mod (d+1) forward with components 1..d, then the exact
  * reverse), then delta from one forward colour-ordered Gauss-Seidel sweep
- * on C started from 0 for B u - C p - g, and p += omega delta. */
+ * on C started from 0 for B u - C p - g, and p += omega delta.  For the
+ * gradient and interface forms, whose point-diagonal blocks are diagonal,
+ * the first backward colour phase repeats an exact solve of the last
+ * forward one and is skipped (a no-op in exact arithmetic). */
 int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps,
                void* x, const void* b, iss_stream_t stream);
 

@@ -1402,7 +1402,7 @@ int iss_smooth_timed(iss_problem* p, int form, int level, int prec, int nsteps, 
         if (e == hipSuccess) e = hipEventRecord(st1, s);
         if (e == hipSuccess) e = hipEventSynchronize(st1);
         float t = 0;
-        for (int q = 0; q < nph && e == hipSuccess; ++q) {
+        for (int q = 0; q < tm.used && e == hipSuccess; ++q) {
             e = hipEventElapsedTime(&t, tm.begin[q], tm.end[q]);
             phase_ms += t;
             ++nphase;

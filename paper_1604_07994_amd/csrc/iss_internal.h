@@ -55,9 +55,11 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
                          size_t bytes32);
 hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec,
                    const void* x, const void* b, void* y, hipStream_t s);
-// events around the 2 (d+1) bulk velocity colour-phase launches of a step
+// events around the bulk velocity colour-phase launches of a step (at most
+// 2 (d+1)); `used` counts the pairs recorded by the last step
 struct PhaseTimer {
     hipEvent_t begin[8], end[8];
+    int used = 0;
 };
 // one Uzawa step on split-layout vectors xs, bs (d+1 fields of Ns each);
 // ws holds d+1 split fields of scratch.  first_step: the first step of a

@@ -1608,8 +1608,8 @@ static inline void counted(const LevelView& L, int kind) {
 }
 
 // One Uzawa step (eq. Uzawa_smooth) on split-layout vectors: symmetric
-// velocity sweep (forward colours 0..d, backward d..0; bulk then special
-// launch per colour), then the pressure forward sweep on C from delta = 0
+// velocity sweep (forward colours 0..d, backward d..0, the repeated colour d
+// skipped where it is a no-op; bulk then special launch per colour), then the pressure forward sweep on C from delta = 0
 // (colour 0 inside the s pass), p += omega delta.  ws holds d + 1 split
 // fields: g = f - B^T p in fields 0..d-1 during the velocity sweep,
 // s = B u - C p - g in field 0 and delta in field d during the pressure
@@ -1630,12 +1630,23 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
         hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, g);
         counted(L, ISS_L_VEL_RHS);
     }
+    // The backward sweep starts with the colour the forward sweep ended
+    // with.  Where every point-diagonal block is diagonal (gradient and
+    // interface forms: the a_tr block of a vertex with itself is
+    // mu |grad phi|^2 I), that phase repeats an exact solve of rows whose
+    // neighbours have not changed, so it is a no-op in exact arithmetic and
+    // is skipped (bulk rows would reproduce the same bits; special rows
+    // would add a rounding-level correction).  The strain form's coupled
+    // block with the reversed component order is not idempotent: it runs.
+    constexpr int first_bwd = (F == FORM_STRAIN) ? 0 : 1;
+    if (tm) tm->used = 0;
     for (int pass = 0; pass < 2; ++pass) {
-        for (int cc = 0; cc <= D; ++cc) {
+        for (int cc = (pass == 0 ? 0 : first_bwd); cc <= D; ++cc) {
             const int c = pass == 0 ? cc : D - cc;
             const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
             const int64_t nsw = special_blocks(L.spec_off[c + 1] - L.spec_off[c], SPEC_WG);
-            if (tm) (void)hipEventRecord(tm->begin[pass * (D + 1) + cc], s);
+            const int tq = tm ? tm->used++ : 0;
+            if (tm) (void)hipEventRecord(tm->begin[tq], s);
             if (merge && bc > 0 && ns > 0) {
                 if (pass == 0)
                     hipLaunchKernelGGL((k_gs_vel_m<D, F, false, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c,
@@ -1644,7 +1655,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                     hipLaunchKernelGGL((k_gs_vel_m<D, F, true, T>), dim3((unsigned)(4 * bc + nsw)), dim3(64), 0, s, L, c,
                                        xs, g, bs, bc);
                 counted(L, ISS_L_GS_VEL_MERGED);
-                if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
+                if (tm) (void)hipEventRecord(tm->end[tq], s);
             } else {
                 if (bc > 0) {
                     if (pass == 0)
@@ -1653,7 +1664,7 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                         hipLaunchKernelGGL((k_gs_vel_s<D, F, true, T>), dim3((unsigned)bc), dim3(256), 0, s, L, c, xs, g);
                     counted(L, ISS_L_GS_VEL_BULK);
                 }
-                if (tm) (void)hipEventRecord(tm->end[pass * (D + 1) + cc], s);
+                if (tm) (void)hipEventRecord(tm->end[tq], s);
                 if (ns > 0) {
                     if (pass == 0)
                         hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L,
