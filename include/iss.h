@@ -193,6 +193,25 @@ int iss_residual(iss_problem* p, int form, int level, int prec, const void* x,
 int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps,
                void* x, const void* b, iss_stream_t stream);
 
+/* iss_smooth without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments and results are those of
+ * iss_smooth.  The colour-split copies of x and b and the smoother's work
+ * fields, 3 (dim+1) Ns elements of the precision's size (Ns = the split
+ * length of the level: (dim+1) ceil((n+1)/(dim+1)) (n+1)^(dim-1)), live in
+ * one static device array of ISS_NOALLOC_SCRATCH_BYTES per GPU, held until
+ * the process ends; a level that needs more returns ISS_E_INVAL (3D: up to
+ * 65^3 in FP64, 2D: up to 513^2 in FP64).  The call makes no hipMalloc,
+ * hipFree or other allocation; it must be made on the device current when
+ * the problem was created (ISS_E_INVAL otherwise).  Every call on one GPU
+ * uses that GPU's single array: calls that overlap on one GPU (several
+ * streams, threads or problems) race and must be serialised by the caller.
+ * The array keeps the last call's contents; the call clears what it needs
+ * cleared itself. */
+#define ISS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int iss_smooth_noalloc(iss_problem* p, int form, int level, int prec, int nsteps,
+                       void* x, const void* b, iss_stream_t stream);
+
 /* Same as iss_smooth, for measurement: HIP events recorded on `stream`
  * around every bulk velocity colour-phase launch and around every step.
  * ms[0] receives the average duration of one bulk velocity colour-phase

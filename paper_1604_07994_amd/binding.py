@@ -55,7 +55,8 @@ EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "
            "iss_dot", "iss_last_error", "iss_net_create", "iss_net_destroy", "iss_net_info",
            "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
            "iss_net_targets", "iss_net_backward", "iss_adam_step", "iss_problem_set_net",
-           "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed", "iss_launch_counts"]
+           "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed", "iss_launch_counts",
+           "iss_smooth_noalloc"]
 
 
 def lib():
@@ -84,6 +85,7 @@ def lib():
     L.iss_apply.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
     L.iss_residual.argtypes = [vp, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl), vp]
     L.iss_smooth.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
+    L.iss_smooth_noalloc.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
     L.iss_smooth_timed.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl)]
     L.iss_restrict.argtypes = [vp, cint, cint, vp, vp, vp]
     L.iss_prolong_add.argtypes = [vp, cint, cint, vp, vp, vp]
@@ -235,6 +237,14 @@ class Problem:
         level = self.levels if level is None else level
         _check(lib().iss_smooth(self._h, FORMS[form], level, _prec(x), nsteps,
                                 self._vec(x, level), self._vec(b, level), _stream()))
+        return x
+
+    def smooth_noalloc(self, form, x, b, nsteps=1, level=None):
+        """iss_smooth_noalloc: the same steps as smooth() with the library's
+        static per-GPU scratch (no allocation; levels up to its size)."""
+        level = self.levels if level is None else level
+        _check(lib().iss_smooth_noalloc(self._h, FORMS[form], level, _prec(x), nsteps,
+                                        self._vec(x, level), self._vec(b, level), _stream()))
         return x
 
     def smooth_timed(self, form, x, b, nsteps=1, level=None):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,12 @@
 #include "iss_internal.h"
 
 using namespace iss;
+
+// Scratch of iss_smooth_noalloc: the colour-split copies of x and b and the
+// smoother's work fields.  One copy per GPU, held by the code object until
+// the process ends.  In host code this name is a stand-in, not a device
+// address: kernels get the address hipGetSymbolAddress returns for it.
+static __device__ __align__(256) char scratch[ISS_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -244,6 +251,8 @@ struct iss_problem {
     VGraph vgraph[3][3];
     hipStream_t cap_stream = nullptr;
     int64_t launch_count[ISS_L_KINDS] = {};   // smoother launches per kernel shape
+    int device = 0;                 // HIP device current at creation
+    void* scratch_dev = nullptr;    // that device's address of `scratch`
     std::vector<void*> allocs;
 };
 
@@ -253,6 +262,27 @@ struct iss_net {
 };
 
 namespace {
+
+// Device address of `scratch` on the current device, resolved once per
+// device (each GPU holds its own copy at its own address).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_address(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(ISS_E_INVAL, "device id out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ISS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ISS_OK;
+}
 
 int dev_alloc(iss_problem* p, void** ptr, size_t bytes) {
     *ptr = nullptr;
@@ -1220,6 +1250,11 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     }
     int rc = ISS_OK;
     do {
+        {
+            hipError_t e = hipGetDevice(&p->device);
+            if (e != hipSuccess) { rc = fail(ISS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e)); break; }
+            if ((rc = scratch_address(p->device, &p->scratch_dev))) break;
+        }
         std::vector<double> imu(256);
         std::vector<float> mu32(256), imu32(256);
         for (int i = 0; i < 256; ++i) {
@@ -1355,6 +1390,37 @@ int iss_smooth(iss_problem* p, int form, int level, int prec, int nsteps, void* 
     const int nf = p->dim + 1;
     void *xs, *bs, *ws;
     split_buffers(p, level, prec, &xs, &bs, &ws);
+    ISS_HIP(k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s));
+    ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
+    for (int i = 0; i < nsteps; ++i)
+        ISS_HIP(k_smooth_step(L.v, form, prec, p->opt.omega, xs, bs, ws, i == 0, s));
+    ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
+    return ISS_OK;
+}
+
+int iss_smooth_noalloc(iss_problem* p, int form, int level, int prec, int nsteps, void* x, const void* b,
+                       iss_stream_t stream) {
+    if (!p || !x || !b || nsteps < 0) return fail(ISS_E_INVAL, "bad argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = check_prec(prec)) || (rc = check_level(p, level))) return rc;
+    Level& L = p->lv[level];
+    const int nf = p->dim + 1;
+    const size_t vec = (size_t)nf * L.v.Ns * prec_bytes(prec);
+    if (3 * vec > (size_t)ISS_NOALLOC_SCRATCH_BYTES)
+        return fail(ISS_E_INVAL, "level too large for the no-allocation scratch (" +
+                                     std::to_string(3 * vec) + " > " +
+                                     std::to_string((size_t)ISS_NOALLOC_SCRATCH_BYTES) + " bytes)");
+    if (!p->scratch_dev) return fail(ISS_E_HIP, "no-allocation scratch address not resolved");
+    int cur = -1;
+    ISS_HIP(hipGetDevice(&cur));
+    if (cur != p->device) return fail(ISS_E_INVAL, "call on another device than the problem's");
+    const hipStream_t s = (hipStream_t)stream;
+    // the same steps as iss_smooth on the device-resident scratch; the
+    // first step clears the pressure correction field with a fill kernel
+    char* base = (char*)p->scratch_dev;
+    void* xs = base;
+    void* bs = base + vec;
+    void* ws = base + 2 * vec;
     ISS_HIP(k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s));
     ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
     for (int i = 0; i < nsteps; ++i)
