@@ -860,6 +860,202 @@ __global__ __launch_bounds__(256) void k_p_rhs_g(LevelView L, const T* __restric
     }
 }
 
+// ----------------------------------------------------------------------------
+// LDS-tiled z-marching right-hand-side passes of the levels above 65^3 (3D).
+//
+// A workgroup owns a tile of ZT_X canonical x positions by ZT_Y rows and a
+// chunk of ZT_Z planes of the interior.  The planes k-1, k, k+1 of every
+// field its stencils read sit in LDS (a ring of three plane slots holding
+// the tile and a one-vertex ring around it), so every value comes from
+// memory once per tile instead of once per stencil entry, with full-width
+// loads.  The loads of plane k+2 are issued before plane k is computed and
+// stored to the freed slot after it.  Workgroup b runs on XCD b % 8; each
+// XCD walks a slab of tile rows (x tiles fastest, then rows, then z
+// chunks), so the tiles whose rings overlap share its L2.
+constexpr int ZT_X = 64, ZT_Y = 4;
+constexpr int ZT_W = ZT_X + 2, ZT_H = ZT_Y + 2, ZT_A = ZT_W * ZT_H;
+constexpr int ZT_PER = (ZT_A + 255) / 256;   // loads per thread per field plane
+
+struct ZTileGrid {
+    int gx, gy, gys, gz, zc;   // tiles along x, y (per XCD slab), z chunks of zc planes
+};
+
+// The z chunk is as long as possible (each chunk reloads two ring planes)
+// while the grid still offers about four workgroups per CU: 8 to 32 planes.
+inline ZTileGrid ztile_grid(int n) {
+    const int m = n - 1;
+    ZTileGrid g;
+    g.gx = (m + ZT_X - 1) / ZT_X;
+    g.gy = (m + ZT_Y - 1) / ZT_Y;
+    g.gys = (g.gy + NXCD - 1) / NXCD;
+    const int per_layer = NXCD * g.gx * g.gys;
+    const int want = std::max(1, (1024 + per_layer - 1) / per_layer);
+    g.zc = std::min(32, std::max(8, (m + want - 1) / want));
+    g.gz = (m + g.zc - 1) / g.zc;
+    return g;
+}
+
+// tile origin (interior coordinates start at 1) and plane range of a
+// workgroup; false for the padding workgroups of the last XCD slabs
+__device__ __forceinline__ bool ztile_origin(const LevelView& L, ZTileGrid g, int& i0, int& j0, int& k0, int& k1) {
+    const int bid = (int)blockIdx.x;
+    const int xcd = bid & (NXCD - 1);
+    const int idx = bid / NXCD;
+    const int tx = idx % g.gx;
+    const int r = idx / g.gx;
+    const int ty = xcd * g.gys + r % g.gys;
+    const int tz = r / g.gys;
+    if (ty >= g.gy || tz >= g.gz) return false;
+    i0 = 1 + tx * ZT_X;
+    j0 = 1 + ty * ZT_Y;
+    k0 = 1 + tz * g.zc;
+    k1 = min(k0 + g.zc, L.n);      // planes k0 .. k1-1 (interior ends at n-1)
+    return true;
+}
+
+// split-layout offset of (i, j, k) inside a field (3D, M = 4 colours)
+__device__ __forceinline__ uint32_t sidx3(const LevelView& L, int i, int j, int k) {
+    return (uint32_t)k * (uint32_t)L.Pp + (uint32_t)j * (uint32_t)L.Rp + (uint32_t)(i & 3) * (uint32_t)L.q +
+           (uint32_t)(i >> 2);
+}
+
+// global loads of plane kk of NF fields (fields f0.. of the split vector xs)
+// for this thread's ZT_PER tile entries; entries past the lattice are 0
+template <int NF, typename T, typename C>
+__device__ __forceinline__ void ztile_fetch(const LevelView& L, const T* __restrict__ xs, int f0, int i0, int j0,
+                                            int kk, C (&reg)[NF][ZT_PER]) {
+#pragma unroll
+    for (int q = 0; q < ZT_PER; ++q) {
+        const int e = (int)threadIdx.x + 256 * q;
+        const int r = e / ZT_W, c = e - r * ZT_W;
+        const int ii = i0 - 1 + c, jj = j0 - 1 + r;
+        const bool ok = e < ZT_A && ii <= L.n && jj <= L.n;
+        const uint32_t off = ok ? sidx3(L, ii, jj, kk) : 0u;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const C v = (C)ld32(xs + (int64_t)(f0 + f) * L.Ns, off);
+            reg[f][q] = ok ? v : (C)0;
+        }
+    }
+}
+
+template <int NF, typename C>
+__device__ __forceinline__ void ztile_store(C (*lds)[3][ZT_A], int slot, const C (&reg)[NF][ZT_PER]) {
+#pragma unroll
+    for (int q = 0; q < ZT_PER; ++q) {
+        const int e = (int)threadIdx.x + 256 * q;
+        if (e < ZT_A) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) lds[f][slot][e] = reg[f][q];
+        }
+    }
+}
+
+// The z march shared by the tiled passes: fills the ring of plane slots and
+// calls body(i, j, k, slot of k-1, slot of k, slot of k+1, active) for
+// every plane of the chunk (every thread of the workgroup takes part; the
+// body writes only if active).
+template <int NF, typename T, typename C, typename Body>
+__device__ __forceinline__ void ztile_march(const LevelView& L, ZTileGrid zg, const T* __restrict__ xs, int f0,
+                                            C (*lds)[3][ZT_A], Body&& body) {
+    int i0, j0, k0, k1;
+    if (!ztile_origin(L, zg, i0, j0, k0, k1)) return;
+    const int tx = (int)threadIdx.x & (ZT_X - 1), ty = (int)threadIdx.x / ZT_X;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = i <= L.n - 1 && j <= L.n - 1;
+    C reg[NF][ZT_PER];
+    for (int p = 0; p < 3; ++p) {
+        ztile_fetch<NF, T, C>(L, xs, f0, i0, j0, k0 - 1 + p, reg);
+        ztile_store<NF, C>(lds, p, reg);
+    }
+    __syncthreads();
+    int sm = 0, s0 = 1, sp = 2;
+    for (int k = k0; k < k1; ++k) {
+        const bool pre = k + 1 < k1;
+        if (pre) ztile_fetch<NF, T, C>(L, xs, f0, i0, j0, k + 2, reg);
+        body(i, j, k, sm, s0, sp, active);
+        __syncthreads();
+        if (pre) ztile_store<NF, C>(lds, sm, reg);
+        __syncthreads();
+        const int t = sm;
+        sm = s0;
+        s0 = sp;
+        sp = t;
+    }
+}
+
+// s = B u - C p - g on interior isoviscous vertices, colour 0 finishing its
+// first pressure Gauss-Seidel phase (delta = s / C_vv), as k_p_rhs_g.
+template <typename T>
+__global__ __launch_bounds__(256) void k_p_rhs_z(LevelView L, ZTileGrid zg, const T* __restrict__ xs,
+                                                 const T* __restrict__ bs, T* __restrict__ sres, T* __restrict__ delta) {
+    using C = typename Acc<T>::type;
+    constexpr int D = 3;
+    __shared__ C lds[D + 1][3][ZT_A];
+    const C sdv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
+    const C vol = (C)kuhn_volume<D>();
+    constexpr int c0 = sc_int<D>(0);
+    ztile_march<D + 1, T, C>(L, zg, xs, 0, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+        const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
+        C dv = 0, cp = 0;
+        static_for<0, KuhnTables<D>::NB>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
+            const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+            const int e = cen + dy * ZT_W + dx;
+            static_for<0, D>([&](auto fc) {
+                constexpr int f = decltype(fc)::value;
+                constexpr int w = sdiv_int<D>(f, o);
+                if constexpr (w != 0) dv += (C)w * lds[f][slot][e];
+            });
+            constexpr int wc = sc_int<D>(o);
+            if constexpr (wc != 0) cp += (C)wc * lds[D][slot][e];
+        });
+        if (!active) return;
+        const uint32_t v = sidx3(L, i, j, k);
+        const int ph = L.vphase_s[v];
+        if (ph == SPECIAL) return;
+        const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
+        const C sv = sdv * dv - sci * (vol * cp) - (C)ld32(bs + (int64_t)D * L.Ns, v);
+        if (((i + j + k) & 3) == 0) delta[v] = (T)(sv / (sci * (vol * (C)c0)));
+        else sres[v] = (T)sv;
+    });
+}
+
+// g = f - B^T p on interior isoviscous vertices, as k_vel_rhs_s.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vel_rhs_z(LevelView L, ZTileGrid zg, const T* __restrict__ xs,
+                                                   const T* __restrict__ bs, T* __restrict__ g) {
+    using C = typename Acc<T>::type;
+    constexpr int D = 3;
+    __shared__ C lds[1][3][ZT_A];
+    const C sbv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
+    ztile_march<1, T, C>(L, zg, xs, D, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+        const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
+        C acc[D] = {0, 0, 0};
+        static_for<0, KuhnTables<D>::NB>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
+            constexpr bool used = sbt_int<D>(0, o) != 0 || sbt_int<D>(1, o) != 0 || sbt_int<D>(2, o) != 0;
+            if constexpr (used) {
+                const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+                const C pv = lds[0][slot][cen + dy * ZT_W + dx];
+                static_for<0, D>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    constexpr int w = sbt_int<D>(l, o);
+                    if constexpr (w != 0) acc[l] += (C)w * pv;
+                });
+            }
+        });
+        if (!active) return;
+        const uint32_t v = sidx3(L, i, j, k);
+        if (L.vphase_s[v] == SPECIAL) return;
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+            g[(int64_t)l * L.Ns + v] = (T)((C)ld32(bs + (int64_t)l * L.Ns, v) - sbv * acc[l]);
+    });
+}
+
 template <int D, int F, bool BWD, typename T>
 __device__ __forceinline__ void gs_vel_body(const LevelView& L, int colour, int64_t bid, int tid,
                                             T* __restrict__ xs, const T* __restrict__ g) {
@@ -1626,7 +1822,14 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
     T* sres = ws;
     T* delta = ws + (int64_t)D * L.Ns;
     const bool merge = L.n <= L.merge_max_n;     // one launch per colour phase
-    if (ba > 0) {
+    // LDS-tiled right-hand-side passes on the large 3D levels
+    const bool ztiled = D == 3 && !merge && L.n >= 2;
+    const ZTileGrid zg = ztile_grid(L.n);
+    const unsigned bz = (unsigned)(NXCD * zg.gx * zg.gys * zg.gz);
+    if (ztiled) {
+        hipLaunchKernelGGL((k_vel_rhs_z<T>), dim3(bz), dim3(256), 0, s, L, zg, xs, bs, g);
+        counted(L, ISS_L_VEL_RHS);
+    } else if (ba > 0) {
         hipLaunchKernelGGL((k_vel_rhs_s<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, g);
         counted(L, ISS_L_VEL_RHS);
     }
@@ -1691,7 +1894,10 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                 counted(L, ISS_L_P_RHS_MERGED);
                 continue;
             }
-            if (ba > 0) {
+            if (ztiled) {
+                hipLaunchKernelGGL((k_p_rhs_z<T>), dim3(bz), dim3(256), 0, s, L, zg, xs, bs, sres, delta);
+                counted(L, ISS_L_P_RHS_GROUPED);
+            } else if (ba > 0) {
                 hipLaunchKernelGGL((k_p_rhs_g<D, T>), dim3((unsigned)ba), dim3(256), 0, s, L, xs, bs, sres, delta);
                 counted(L, ISS_L_P_RHS_GROUPED);
             }
