@@ -2,15 +2,17 @@
 (interface) vs strain form, on one MI355X.
 
 Workload (default): sinker_3d -- unit cube as 2 x 2 x 2 macro cubes (48 Kuhn
-tetrahedra) refined 7 times (257^3 vertices, 6.67e7 unknowns u, v, w, p),
+tetrahedra) refined 7 times (257^3 vertices, 6.79e7 unknowns u, v, w, p),
 8 seeded spheres (seed 0) with viscosity 1e4 inside and 1 outside, buoyancy
 rho = 1 inside, no-slip walls.  Synthetic, seeded, generated on the device by
 the library (iss_rhs_buoyancy).  One "step" is one complete solve from x = 0
 to ||b - K x|| <= 1e-8 ||b|| with the interface (decoupled + a_tr interface
-rows) form in FP64: FGMRES(150) with one Uzawa V(5,5) cycle per iteration
-(omega 0.6, element-averaged coarse viscosity, strain form on the coarser
-levels as in the paper's coarse-grid swap); the strain form is timed with the
-same solver.
+rows) form in FP64: FGMRES(150) preconditioned by two stationary Uzawa
+V_var(4,4) cycles (two more smoothing steps per coarser level, omega 0.7,
+element-averaged coarse viscosity, strain form on every level below the
+finest); the strain form is timed with the same solver.  The paper's own
+configuration (a_tr on every level but the coarsest) is run once for the
+record.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
@@ -36,16 +38,24 @@ def parse():
     ap.add_argument("--workload", default="sinker_3d")
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--omega", type=float, default=0.6)
+    ap.add_argument("--omega", type=float, default=0.7)
     ap.add_argument("--nu", type=int, default=4, help="pre- and post-smoothing steps")
     ap.add_argument("--nu-inc", type=int, default=2,
                     help="variable V-cycle: extra smoothing steps per level below the finest")
+    ap.add_argument("--cycles", type=int, default=2, help="stationary V-cycles per preconditioner application")
+    ap.add_argument("--mid-form", default="strain", choices=["same", "strain", "interface", "gradient"],
+                    help="viscous form of the levels between the finest and the coarsest")
+    ap.add_argument("--rate-iters", type=int, default=200,
+                    help="cycles of the asymptotic-rate measurement (0: skip)")
+    ap.add_argument("--no-paper-config", action="store_true",
+                    help="skip the run with a_tr on every level but the coarsest")
     ap.add_argument("--restart", type=int, default=150)
     ap.add_argument("--maxit", type=int, default=400)
     ap.add_argument("--outer", default="fgmres")
     ap.add_argument("--coarse-mu", default="average", choices=["average", "centroid"])
     ap.add_argument("--forms", default="interface,strain")
-    ap.add_argument("--coarse-form", default="strain", choices=["same", "strain", "interface", "gradient"])
+    ap.add_argument("--coarse-form", default="strain", choices=["same", "strain", "interface", "gradient"],
+                    help="viscous form of the coarsest level (the swap of Sec. 5)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solves: smoothing steps, applies and a plain copy (for profiler runs)")
     ap.add_argument("--reps", type=int, default=5)
@@ -76,10 +86,11 @@ def event_time(fn, reps):
     return s.elapsed_time(e) / reps
 
 
-def cpu_baseline(w, its_gpu, omega, nu, restart, nu_inc=0):
-    """The oracle (explicit CSR, same algorithm) on the host: an FGMRES solve
-    of the same workload at a reduced level, timed, scaled to the full
-    lattice by vertex count and to the GPU's iteration count."""
+def cpu_baseline(w, its_gpu, omega, nu, restart, nu_inc, cycles, mid_form, coarse_form, sample_its=8):
+    """The oracle (explicit CSR, same algorithm and settings) on one host
+    core: FGMRES iterations of the same workload family at 65^3 (the 257^3
+    CSR would need ~40 GB), timed, and scaled to the full lattice by vertex
+    count and to the GPU's iteration count."""
     code = r"""
 import json, sys, time, numpy as np
 sys.path.insert(0, %r)
@@ -87,28 +98,30 @@ import iss_inputs
 from oracle import multigrid as mg, problem as oprob
 w = iss_inputs.workload(%r, seed=%d, levels=%d)
 H = mg.Hierarchy(w['dim'], w['macro'], w['levels'], w['coarse'], w['inclusions'], w['mu'], 'interface',
-                 omega=%r, nu1=%d, nu2=%d, coarse_mu='average', coarse_form='strain', nu_inc=%d)
+                 omega=%r, nu1=%d, nu2=%d, coarse_mu='average', coarse_form=%r, mid_form=%r, nu_inc=%d)
 lv = H.levels[w['levels']]
 b = oprob.rhs_buoyancy(w['dim'], w['n'], lv.disc.elems, lv.disc.phase_e, w['buoyant']) * lv.free
 t = time.time()
-x, h = mg.solve_fgmres(H, b, rtol=1e-8, restart=%d, maxit=%d)
+x, h = mg.solve_fgmres(H, b, rtol=1e-8, restart=%d, maxit=%d, cycles=%d)
 dt = time.time() - t
 print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h[-1])}))
 """
     lv_small = min(w["levels"], 5)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, nu_inc, restart, 20)
-    out = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, env=env, timeout=600)
+    src = code % (ROOT, w["name"], w.get("seed", 0), lv_small, omega, nu, nu, coarse_form, mid_form, nu_inc,
+                  restart, sample_its, cycles)
+    out = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, env=env, timeout=900)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
     r = json.loads(out.stdout.strip().splitlines()[-1])
     per_it_vertex = r["seconds"] / max(r["its"], 1) / r["N"]
     N_full = (w["n"] + 1) ** w["dim"]
     est = per_it_vertex * N_full * its_gpu
-    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": "oracle FGMRES + Uzawa V-cycle (same settings) on %s refined %d times (%d vertices), %d iterations "
-                      "in %.1f s, scaled by vertex count to %d vertices and to the GPU's %d "
-                      "iterations" % (w["name"], lv_small, r["N"], r["its"], r["seconds"], N_full, its_gpu)}
+    return {"value": est, "unit": "s", "cores": 1, "host_nproc": os.cpu_count(), "kind": "oracle",
+            "sample": "oracle FGMRES with the same preconditioner (%d stationary V-cycles, same smoothing and "
+                      "coarse settings) on %s refined %d times (%d vertices): %d iterations in %.1f s on one "
+                      "core, scaled by vertex count to %d vertices and to the GPU's %d iterations"
+                      % (cycles, w["name"], lv_small, r["N"], r["its"], r["seconds"], N_full, its_gpu)}
 
 
 def measured_traffic(kernel, form):
@@ -163,9 +176,11 @@ def main():
     dev = torch.device("cuda:0")
     forms = args.forms.split(",")
     t0 = time.time()
+    mid_form = None if args.mid_form == "same" else args.mid_form
+    coarse_form = None if args.coarse_form == "same" else args.coarse_form
     P = Problem.from_workload(w, outer=args.outer, omega=args.omega, restart=args.restart,
                               coarse_mu=args.coarse_mu, nu1=args.nu, nu2=args.nu, nu_inc=args.nu_inc,
-                              coarse_form=None if args.coarse_form == "same" else args.coarse_form)
+                              coarse_form=coarse_form, mid_form=mid_form, cycles=args.cycles)
     log("setup %.1f s, n = %d" % (time.time() - t0, w["n"]))
     nvec = P.vector_size()
     N = P.num_vertices()
@@ -245,6 +260,20 @@ def main():
     if not args.no_learned:
         learned = learned_report()
 
+    # asymptotic rate of the stationary cycle per form (Sec. 5: residual
+    # reduction per cycle of the homogeneous problem, rescaled every cycle)
+    rates = None
+    if args.rate_iters > 0:
+        import iss_inputs as _inp
+        rates = {}
+        x0 = torch.from_numpy(_inp.random_vector(w["dim"], w["n"], seed=7)).to(dev)
+        for form in forms:
+            xr0 = x0.clone()
+            hist = P.asymptotic_rate(form, xr0, iters=args.rate_iters)
+            rates[form] = {"rate": hist[-1], "mean_last_20": sum(hist[-20:]) / len(hist[-20:]),
+                           "iterations": args.rate_iters}
+        log("asymptotic rates: %s" % rates)
+
     apply_gbs = {}
     smooth_ms = {}
     if not args.quick:
@@ -263,31 +292,59 @@ def main():
         log("apply GB/s: %s" % {k: round(v["GBs"], 1) for k, v in apply_gbs.items()})
         log("smoothing (HIP events): %s" % smooth_ms)
 
+    # the paper's own configuration: a_tr (the call's form) on every level
+    # but the coarsest, which takes the strain form (Sec. 5); one cycle per
+    # FGMRES iteration, for the record
+    paper_cfg = None
+    if not args.no_paper_config and "interface" in forms:
+        P.close()
+        torch.cuda.empty_cache()
+        Pp = Problem.from_workload(w, outer=args.outer, omega=args.omega, restart=40,
+                                   coarse_mu=args.coarse_mu, nu1=args.nu, nu2=args.nu, nu_inc=args.nu_inc,
+                                   coarse_form="strain", mid_form=None, cycles=1)
+        x.zero_()
+        info = Pp.solve("interface", x, b, rtol=1e-8, maxit=150, raise_on_fail=False)
+        paper_cfg = {"config": "a_tr on every level but the coarsest (strain form there), one V-cycle per "
+                               "FGMRES(40) iteration, maxit 150",
+                     "iterations": info["iterations"], "relres": info["relres"], "status": info["status"],
+                     "seconds": info["seconds"]}
+        log("paper configuration: its %d relres %.2e status %d" % (info["iterations"], info["relres"],
+                                                                   info["status"]))
+        Pp.close()
+
     main_form = forms[0]
     value = results[main_form]["seconds"]
-    # roofline of the dominant kernel: the bulk velocity Gauss-Seidel colour
-    # phase (k_gs_vel_s; the largest kernel-time share of a solve).  One
-    # launch updates the interior isoviscous vertices of one colour class;
-    # it must read the three velocity fields on the two neighbouring colour
-    # classes (2 x 24 B per class vertex), g = f - B^T p (24 B) and the phase
-    # byte on its own class, and write its class (24 B): 97 B per class
-    # vertex, i.e. 97 / 4 B per interior lattice vertex.
-    roof = None
+    # Roofline of the dominant kernel, the bulk velocity Gauss-Seidel colour
+    # phase (k_gs_vel_s; the largest kernel-time share of a solve), on the
+    # method's algorithmic bytes: a velocity Gauss-Seidel sweep over all
+    # colours must read u (3 fields), f (3) and p (for B^T p) and write u (3):
+    # 10 values of 8 B plus the phase byte = 81 B per vertex per sweep, so
+    # one of the d+1 colour-phase launches of a sweep is charged 81/(d+1) B
+    # per interior vertex.  The whole smoothing step is charged the
+    # symmetric sweep (162 B) plus the pressure Uzawa step (u, p, g read,
+    # p written, phase: 49 B) = 211 B per interior vertex.
+    roof = roof_step = None
     if smooth_ms:
         n_int = (w["n"] - 1) ** w["dim"]
-        bytes_launch = 97.0 / (w["dim"] + 1) * n_int
+        bytes_launch = 81.0 / (w["dim"] + 1) * n_int
         ms = smooth_ms[main_form]["velocity_colour_phase_ms"]
         ach = bytes_launch / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm",
                 "kernel": "k_gs_vel_s (%s form, bulk velocity colour phase, finest level, FP64)" % main_form,
-                "algorithmic_bytes_per_launch": bytes_launch, "bytes_per_class_vertex": 97,
+                "algorithmic_bytes_per_launch": bytes_launch, "bytes_per_vertex_per_sweep": 81,
                 "ms_per_launch": ms, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic("k_gs_vel_s", main_form)}
+        step_bytes = 211.0 * n_int
+        st = smooth_ms[main_form]["step_ms"]
+        roof_step = {"bound": "hbm", "what": "one Uzawa smoothing step, finest level, FP64, all kernels",
+                     "algorithmic_bytes": step_bytes, "bytes_per_vertex": 211, "ms": st,
+                     "achieved": step_bytes / (st * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": step_bytes / (st * 1e-3) / 1e9 / PEAK_HBM_GBS}
     cpu = None
     if not args.no_cpu:
         try:
             cpu = cpu_baseline(w, results[main_form]["iterations"], args.omega, args.nu, args.restart,
-                               args.nu_inc)
+                               args.nu_inc, args.cycles, mid_form, coarse_form)
         except Exception as e:   # reported, never silently replaced
             cpu = {"error": str(e)[-300:]}
     out = {
@@ -298,10 +355,11 @@ def main():
         "config": {"workload": "%s: %d^3 vertices, %d unknowns, %d spheres mu_in %.0e, %d interface "
                                "vertices" % (w["name"], w["n"] + 1, nvec, len(w["inclusions"]),
                                              w["mu"][1], nif),
-                   "solver": "%s + Uzawa V(%d,%d) +%d steps per coarser level, omega %.2f, restart %d, "
-                             "coarse viscosity %s"
-                             % (args.outer, args.nu, args.nu, args.nu_inc, args.omega, args.restart,
-                                args.coarse_mu),
+                   "solver": "%s(%d), preconditioner %d stationary Uzawa V(%d,%d) cycles +%d steps per "
+                             "coarser level, omega %.2f, coarse viscosity %s, levels below the finest in the "
+                             "%s form, coarsest in the %s form"
+                             % (args.outer, args.restart, args.cycles, args.nu, args.nu, args.nu_inc, args.omega,
+                                args.coarse_mu, args.mid_form, args.coarse_form),
                    "parallelism": "single GPU"},
         "forms": results,
         "strain_over_interface": (results["strain"]["seconds"] / results["interface"]["seconds"])
@@ -310,7 +368,10 @@ def main():
         "learned_correction": learned,
         "apply": apply_gbs,
         "smooth_step_ms": smooth_ms,
+        "paper_configuration": paper_cfg,
+        "asymptotic_rate": rates,
         "roofline": roof,
+        "roofline_smoothing_step": roof_step,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

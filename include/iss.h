@@ -114,17 +114,23 @@ typedef struct {
                            * finest and the coarsest inside V-cycles: -1
                            * (default) = the form of the call (Sec. 5 keeps
                            * the stencil form on the finer grids). */
-    int merge_max_n;      /* kernel shapes of the smoother (results are the
-                           * same for every setting): levels with n <=
-                           * merge_max_n cells per axis launch each colour
-                           * phase as one merged grid of bulk and special
-                           * rows, larger levels launch bulk and special
-                           * rows separately with the grouped pressure
-                           * right-hand-side pass.  Default 64; 0 selects
-                           * the large-level kernels on every level. */
+    int merge_max_n;      /* kernel shapes (results are the same for every
+                           * setting up to rounding order): levels with
+                           * n <= merge_max_n cells per axis launch each
+                           * colour phase of the smoother as one merged grid
+                           * of bulk and special rows and the bulk rows of
+                           * applies and residuals one vertex per thread;
+                           * larger levels launch bulk and special rows
+                           * separately, with the LDS-tiled right-hand-side
+                           * passes and applies in 3D.  Default 64; 0
+                           * selects the large-level kernels everywhere. */
     int spec_wide_min;    /* pressure special-row colour lists longer than
                            * this run in 256-thread workgroups, shorter ones
                            * in one-wave workgroups.  Default 65536. */
+    int cycles;           /* V-cycles per preconditioner application inside
+                           * iss_solve: z = the iterate after `cycles` steps
+                           * of the stationary V-cycle iteration on K z = r
+                           * from z = 0 (default 1). */
 } iss_options;
 
 typedef struct {
@@ -259,6 +265,23 @@ int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b,
 int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
               const double* b, iss_solve_info* info, iss_stream_t stream);
 
+/* Asymptotic convergence rate of the stationary V-cycle iteration, measured
+ * as in Sec. 5 (the residual reduction per cycle of the homogeneous
+ * problem after many cycles, the iterate rescaled every cycle).  x (FP64
+ * device vector, velocity zero on the boundary) is the start and is
+ * overwritten; each of the iters steps runs one FP64 V-cycle (options as
+ * in iss_solve) on K x = 0 from x, removes the pressure mean (the
+ * constant pressure spans the kernel of K and passes through the cycle
+ * unchanged), and stores ||K x_new|| / ||K x|| in rates[step] (host array
+ * of iters entries) before rescaling x to ||K x|| = 1.  The last entries
+ * approach the asymptotic rate.  Synchronises every step. */
+int iss_asymptotic_rate(iss_problem* p, int form, int iters, double* x, double* rates,
+                        iss_stream_t stream);
+
+/* y = a x + b y for FP64 device vectors of length n (the vector updates of
+ * callers that drive the solver pieces themselves). */
+int iss_axpby(double a, const double* x, double b, double* y, int64_t n, iss_stream_t stream);
+
 /* Euclidean dot product of two FP64 device vectors of length n. */
 int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double* out,
             iss_stream_t stream);
@@ -279,7 +302,10 @@ int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double*
  * (dx+1) + 3 (dy+1) + 9 (dz+1); 12096 values. */
 typedef struct iss_net iss_net;
 
-/* Create the network state for the finest level of p (band, buffers). */
+/* Create the network state for the finest level of p (band, buffers).  The
+ * network may outlive p: after iss_problem_destroy its input, forward,
+ * target, backward and Adam calls still work, the calls that need the
+ * problem (iss_net_correction, iss_problem_set_net) return ISS_E_INVAL. */
 int iss_net_create(iss_problem* p, iss_net** out);
 void iss_net_destroy(iss_net* net);
 /* Band size M and parameter count. */
@@ -313,25 +339,34 @@ int iss_net_output_grad(iss_net* net, const double* g, double factor, iss_stream
  * n FP32 parameters w with moments m, v and gradient g (device). */
 int iss_adam_step(int64_t n, float* w, float* m, float* v, const float* g, float lr, int step,
                   iss_stream_t stream);
+/* Band rows of the network input set by iss_net_features (M x 8 BF16 bit
+ * patterns, band order, device memory of the caller) out to dst, or back
+ * in from src, so that training inputs can be stored compactly and
+ * replayed without the residual they came from. */
+int iss_net_save_input(iss_net* net, uint16_t* dst, iss_stream_t stream);
+int iss_net_load_input(iss_net* net, const uint16_t* src, iss_stream_t stream);
 /* Attach a network to iss_solve (NULL detaches).  With a network attached
  * the preconditioner is z = V(r) + c, c = the band correction computed from
  * r - K V(r), kept only if it lowers that residual's norm. */
 int iss_problem_set_net(iss_problem* p, iss_net* net);
 
-/* Kernel launches of the smoother, counted per kernel shape on the host
- * at launch time (graph replays of the coarse V-cycle are not counted).
- * Lets a caller confirm which kernel family served a smoothing call. */
+/* Kernel launches of the smoother and of the bulk apply/residual, counted
+ * per kernel shape on the host at launch time (graph replays of the coarse
+ * V-cycle are not counted).  Lets a caller confirm which kernel family
+ * served a call. */
 enum iss_launch_kind {
     ISS_L_VEL_RHS = 0,        /* g = f - B^T p, all interior rows          */
     ISS_L_GS_VEL_BULK,        /* velocity colour phase, bulk rows          */
     ISS_L_GS_VEL_SPECIAL,     /* velocity colour phase, special rows       */
     ISS_L_GS_VEL_MERGED,      /* velocity colour phase, bulk + special     */
-    ISS_L_P_RHS_GROUPED,      /* s = B u - C p - g, grouped (large levels) */
+    ISS_L_P_RHS_GROUPED,      /* s = B u - C p - g on large levels         */
     ISS_L_P_RHS_MERGED,       /* s pass merged with colour-0 special rows  */
     ISS_L_GS_P_BULK,          /* pressure colour phase, bulk rows          */
     ISS_L_GS_P_SPECIAL,       /* pressure special rows, one-wave groups    */
     ISS_L_GS_P_SPECIAL_WIDE,  /* pressure special rows, 256-thread groups  */
     ISS_L_GS_P_MERGED,        /* pressure colour phase, bulk + special     */
+    ISS_L_APPLY_BULK,         /* apply / residual, bulk rows (small levels) */
+    ISS_L_APPLY_TILED,        /* apply / residual, bulk rows, LDS z march   */
     ISS_L_KINDS
 };
 /* Copy the ISS_L_KINDS counters into counts (host, n >= ISS_L_KINDS

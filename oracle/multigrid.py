@@ -290,15 +290,16 @@ class Hierarchy:
             hist.append(np.linalg.norm(residual(lv, x, b)) / nb)
         return x, np.array(hist)
 
-    def asymptotic_rate(self, iters=200, seed=0):
-        """Residual reduction per cycle on the homogeneous problem after
-        ``iters`` cycles, rescaling the iterate every step (Sec. 5)."""
+    def rate_history(self, x0, iters):
+        """Residual reduction of every cycle of the stationary iteration on
+        the homogeneous problem K x = 0 from x0, rescaling the iterate every
+        step (the measurement of Sec. 5); the last entries approach the
+        asymptotic rate."""
         lv = self.levels[self.fine]
-        rng = np.random.default_rng(seed)
-        x = rng.uniform(-1, 1, lv.K.shape[0]) * lv.free
+        x = np.array(x0, dtype=np.float64) * lv.free
         b = np.zeros_like(x)
-        rate = np.nan
         N = lv.N
+        rates = []
         for _ in range(iters):
             r0 = np.linalg.norm(lv.K @ x)
             x = self.vcycle(self.fine, x, b)
@@ -306,9 +307,16 @@ class Hierarchy:
             # the rescaling does not let it grow without bound
             x[self.dim * N:] -= np.dot(lv.weights, x[self.dim * N:]) / lv.weights.sum()
             r1 = np.linalg.norm(lv.K @ x)
-            rate = r1 / r0
+            rates.append(r1 / r0)
             x /= r1
-        return rate
+        return np.array(rates)
+
+    def asymptotic_rate(self, iters=200, seed=0):
+        """Residual reduction per cycle on the homogeneous problem after
+        ``iters`` cycles, rescaling the iterate every step (Sec. 5)."""
+        lv = self.levels[self.fine]
+        rng = np.random.default_rng(seed)
+        return self.rate_history(rng.uniform(-1, 1, lv.K.shape[0]), iters)[-1]
 
 
 def direct_solve(lv, b):
@@ -373,8 +381,18 @@ def fgmres(apply_K, precond, b, rtol=1e-8, restart=40, maxit=200, x0=None):
     return x, np.array(hist)
 
 
-def solve_fgmres(hier, b, rtol=1e-8, restart=40, maxit=200):
+def stationary_cycles(hier, r, cycles=1):
+    """z after ``cycles`` steps of the stationary V-cycle iteration
+    z <- V(z; r) on K z = r from z = 0 (the preconditioner of the outer
+    Krylov iteration; one step is the plain V-cycle of Sec. 5)."""
+    z = np.zeros_like(r)
+    for _ in range(cycles):
+        z = hier.vcycle(hier.fine, z, r)
+    return z
+
+
+def solve_fgmres(hier, b, rtol=1e-8, restart=40, maxit=200, cycles=1):
     lv = hier.levels[hier.fine]
     return fgmres(lambda v: lv.K @ v,
-                  lambda r: hier.vcycle(hier.fine, np.zeros_like(r), r),
+                  lambda r: stationary_cycles(hier, r, cycles),
                   b, rtol=rtol, restart=restart, maxit=maxit)

@@ -34,12 +34,14 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int),
                 ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int),
-                ("mid_form", ctypes.c_int), ("merge_max_n", ctypes.c_int), ("spec_wide_min", ctypes.c_int)]
+                ("mid_form", ctypes.c_int), ("merge_max_n", ctypes.c_int), ("spec_wide_min", ctypes.c_int),
+                ("cycles", ctypes.c_int)]
 
 
 # iss_launch_kind: smoother kernel shapes counted by iss_launch_counts
 LAUNCH_KINDS = ["vel_rhs", "gs_vel_bulk", "gs_vel_special", "gs_vel_merged", "p_rhs_grouped",
-                "p_rhs_merged", "gs_p_bulk", "gs_p_special", "gs_p_special_wide", "gs_p_merged"]
+                "p_rhs_merged", "gs_p_bulk", "gs_p_special", "gs_p_special_wide", "gs_p_merged",
+                "apply_bulk", "apply_tiled"]
 
 
 class SolveInfo(ctypes.Structure):
@@ -56,7 +58,8 @@ EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "
            "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
            "iss_net_targets", "iss_net_backward", "iss_adam_step", "iss_problem_set_net",
            "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed", "iss_launch_counts",
-           "iss_smooth_noalloc"]
+           "iss_smooth_noalloc", "iss_asymptotic_rate", "iss_net_save_input", "iss_net_load_input",
+           "iss_axpby"]
 
 
 def lib():
@@ -108,6 +111,10 @@ def lib():
     L.iss_net_correction.argtypes = [vp, vp, vp]
     L.iss_net_output_grad.argtypes = [vp, vp, cdbl, vp]
     L.iss_launch_counts.argtypes = [vp, ctypes.POINTER(i64), cint, cint]
+    L.iss_asymptotic_rate.argtypes = [vp, cint, cint, vp, ctypes.POINTER(cdbl), vp]
+    L.iss_net_save_input.argtypes = [vp, vp, vp]
+    L.iss_net_load_input.argtypes = [vp, vp, vp]
+    L.iss_axpby.argtypes = [cdbl, vp, cdbl, vp, i64, vp]
     _lib = L
     return L
 
@@ -153,12 +160,12 @@ class Problem:
 
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
-                 coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536):
+                 coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536, cycles=1):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
                       -1 if coarse_form is None else FORMS[coarse_form], nu_inc,
-                      -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min)
+                      -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min, cycles)
         incs = inclusions_to_c(inclusions)
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()
@@ -292,12 +299,33 @@ class Problem:
                 "seconds": info.seconds, "history": [hist[i] for i in range(info.history_len)],
                 "net_accepted": info.net_accepted, "net_rejected": info.net_rejected}
 
+    def asymptotic_rate(self, form, x, iters=200):
+        """Residual reduction per stationary V-cycle of the homogeneous
+        problem, rescaled every cycle (iss_asymptotic_rate); x is the start
+        (overwritten).  Returns the list of per-cycle rates."""
+        import torch
+        rates = (ctypes.c_double * iters)()
+        _check(lib().iss_asymptotic_rate(self._h, FORMS[form], iters, self._vec(x, self.levels, torch.float64),
+                                         rates, _stream()))
+        return list(rates)
+
     def launch_counts(self, reset=False):
         """Smoother kernel launches per kernel shape since creation (or the
         last reset), as a dict keyed by LAUNCH_KINDS."""
         c = (ctypes.c_int64 * len(LAUNCH_KINDS))()
         _check(lib().iss_launch_counts(self._h, c, len(LAUNCH_KINDS), int(reset)))
         return dict(zip(LAUNCH_KINDS, list(c)))
+
+    def axpby(self, a, x, b, y):
+        """y = a x + b y (FP64 device vectors of equal length)."""
+        import torch
+        for t in (x, y):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64):
+                raise ValueError("axpby needs contiguous float64 CUDA tensors")
+        if x.numel() != y.numel():
+            raise ValueError("size mismatch")
+        _check(lib().iss_axpby(float(a), _ptr(x), float(b), _ptr(y), y.numel(), _stream()))
+        return y
 
     def dot(self, a, b):
         import torch
@@ -368,6 +396,19 @@ class BandNet:
         _check(lib().iss_net_backward(self._h, _ptr(t) if t is not None else None, _ptr(grad),
                                       ctypes.byref(loss) if t is not None else None, _stream()))
         return loss.value if t is not None else None
+
+    def save_input(self, dst):
+        """Band rows of the current input (M x 8 BF16 bit patterns) into the
+        int16 device tensor dst."""
+        if dst.numel() != self.band_size * 8 or dst.element_size() != 2:
+            raise ValueError("need a 2-byte tensor of band_size * 8 entries")
+        _check(lib().iss_net_save_input(self._h, _ptr(dst), _stream()))
+        return dst
+
+    def load_input(self, src):
+        if src.numel() != self.band_size * 8 or src.element_size() != 2:
+            raise ValueError("need a 2-byte tensor of band_size * 8 entries")
+        _check(lib().iss_net_load_input(self._h, _ptr(src), _stream()))
 
     def correction(self, c):
         _check(lib().iss_net_correction(self._h, _ptr(c), _stream()))

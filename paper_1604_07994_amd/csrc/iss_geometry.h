@@ -189,6 +189,17 @@ constexpr int sc_int(int o) {
             if (K.slot_nb[sl][b] == o) s += kg_dot<D>(K.slot_type[sl], K.slot_loc[sl], b);
     return s;
 }
+// integer part (times |T|) of the viscous stencil of an isoviscous interior
+// vertex, viscosity 1: block (l, k) at footprint offset o, form as kg_visc
+template <int D>
+constexpr int svis_int(int form, int l, int k, int o) {
+    constexpr auto& K = Kuhn<D>::T;
+    int s = 0;
+    for (int sl = 0; sl < KuhnTables<D>::NS; ++sl)
+        for (int b = 0; b <= D; ++b)
+            if (K.slot_nb[sl][b] == o) s += kg_visc<D>(form, K.slot_type[sl], K.slot_loc[sl], l, b, k);
+    return s;
+}
 // footprint index of the offset (dx, dy, dz), or -1
 template <int D>
 constexpr int off_index(int dx, int dy, int dz) {

@@ -148,6 +148,11 @@ int build_tables(ElemTables<D, double>& t) {
     // the right-hand-side kernels use the compile-time integer stencils
     const double vol = kuhn_volume<D>(), bvol = -vol / (D + 1);
     for (int o = 0; o < NB; ++o) {
+        for (int f = 0; f < 3; ++f)
+            for (int l = 0; l < D; ++l)
+                for (int k = 0; k < D; ++k)
+                    if (std::fabs(t.Svis[f][l][k][o] - vol * svis_int<D>(f, l, k, o)) > 1e-13)
+                        return fail(ISS_E_INVAL, "viscous stencil (integer form)");
         if (std::fabs(t.Sc[o] - vol * sc_int<D>(o)) > 1e-13) return fail(ISS_E_INVAL, "C stencil (integer form)");
         for (int k = 0; k < D; ++k) {
             if (std::fabs(t.Sdiv[k][o] - bvol * sdiv_int<D>(k, o)) > 1e-13)
@@ -240,10 +245,12 @@ struct iss_problem {
     double* d_w = nullptr;
     double* d_r = nullptr;
     double* d_h = nullptr;          // m + 2 entries
+    double* d_rate = nullptr;       // asymptotic-rate measurement: b = 0 and K x (2 vectors)
     uint8_t* d_flag = nullptr;      // 256 buoyancy flags
     double* h_pinned = nullptr;     // 8192 doubles of pinned host memory
     int64_t reorth_count = 0;       // second Gram-Schmidt passes (diagnostics)
     iss_net* net = nullptr;         // attached band correction (not owned)
+    std::vector<iss_net*> nets;     // every network created for this problem
     int net_accepted = 0, net_rejected = 0;
     // coarse part of the V-cycle per (form, precision) as a HIP graph;
     // ISS_VCYCLE_GRAPH=0 in the environment at creation turns it off
@@ -928,12 +935,14 @@ int precondition(iss_problem* p, int form, int prec, const double* v, double* z,
     if ((rc = ensure_work(p, l, prec))) return rc;
     Level& L = p->lv[l];
     if (prec == PREC_F64) {
-        if ((rc = vcycle(p, l, form, PREC_F64, z, v, true, s))) return rc;
+        for (int c = 0; c < p->opt.cycles; ++c)
+            if ((rc = vcycle(p, l, form, PREC_F64, z, v, c == 0, s))) return rc;
     } else {
         // FP32 arithmetic, vectors stored in FP32 or BF16 (same exponent
         // range as FP64 needs here, so no scaling)
         ISS_HIP(k_convert(PREC_F64, v, prec, L.w_b[prec], n, s));
-        if ((rc = vcycle(p, l, form, prec, L.w_x[prec], L.w_b[prec], true, s))) return rc;
+        for (int c = 0; c < p->opt.cycles; ++c)
+            if ((rc = vcycle(p, l, form, prec, L.w_x[prec], L.w_b[prec], c == 0, s))) return rc;
         ISS_HIP(k_convert(prec, L.w_x[prec], PREC_F64, z, n, s));
     }
     if (p->net) {
@@ -1180,12 +1189,13 @@ int iss_default_options(iss_options* o) {
     o->mid_form = -1;
     o->merge_max_n = 64;
     o->spec_wide_min = 65536;
+    o->cycles = 1;
     return ISS_OK;
 }
 
 void iss_problem_destroy(iss_problem* p) {
     if (!p) return;
-    if (p->net) p->net->p = nullptr;
+    for (iss_net* nt : p->nets) nt->p = nullptr;     // the networks outlive it
     for (auto& row : p->vgraph)
         for (auto& G : row)
             if (G.exec) (void)hipGraphExecDestroy(G.exec);
@@ -1244,7 +1254,7 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
         (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES) ||
         (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
         p->opt.coarse_form < -1 || p->opt.coarse_form > 2 || p->opt.mid_form < -1 || p->opt.mid_form > 2 ||
-        p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0) {
+        p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0 || p->opt.cycles < 1 || p->opt.cycles > 16) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }
@@ -1525,6 +1535,44 @@ int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double
     return solve(p, form, prec, rtol, maxit, x, b, info, (hipStream_t)stream);
 }
 
+int iss_asymptotic_rate(iss_problem* p, int form, int iters, double* x, double* rates, iss_stream_t stream) {
+    if (!p || !x || !rates || iters < 1) return fail(ISS_E_INVAL, "bad argument");
+    int rc;
+    if ((rc = check_form(form))) return rc;
+    const int l = p->levels, D = p->dim;
+    Level& L = p->lv[l];
+    const int64_t N = L.v.N, n = (int64_t)(D + 1) * N;
+    const hipStream_t s = (hipStream_t)stream;
+    if (!p->d_rate) {
+        if ((rc = dev_alloc(p, (void**)&p->d_rate, (size_t)2 * n * sizeof(double)))) return rc;
+        ISS_HIP(k_fill(PREC_F64, p->d_rate, n, 0.0, s));
+    }
+    const double* zero = p->d_rate;
+    double* y = p->d_rate + n;
+    double sq[4];
+    ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_APPLY, PREC_F64, x, nullptr, y, s));
+    if ((rc = field_norms(p, PREC_F64, y, N, D + 1, sq, s))) return rc;
+    double r0 = total_norm(sq, D + 1);
+    if (!(r0 > 0) || !std::isfinite(r0)) return fail(ISS_E_INVAL, "K x of the initial iterate is zero or not finite");
+    ISS_HIP(k_scale(x, 1.0 / r0, x, n, s));
+    for (int it = 0; it < iters; ++it) {
+        // one stationary cycle on K x = 0, then the constant pressure (the
+        // kernel of K, untouched by the cycle) is removed so that the
+        // rescaling cannot let it grow
+        if ((rc = vcycle(p, l, form, PREC_F64, x, zero, false, s))) return rc;
+        ISS_HIP(k_field_sum(x + (int64_t)D * N, N, p->d_partial, p->d_red, s));
+        ISS_HIP(k_sub_mean(x + (int64_t)D * N, N, p->d_red, s));
+        ISS_HIP(k_apply(L.v, form, BLOCK_FULL, MODE_APPLY, PREC_F64, x, nullptr, y, s));
+        if ((rc = field_norms(p, PREC_F64, y, N, D + 1, sq, s))) return rc;
+        const double r1 = total_norm(sq, D + 1);
+        rates[it] = r1;            // ||K x|| was 1 before the cycle
+        if (!(r1 > 0) || !std::isfinite(r1)) return fail(ISS_E_DIVERGED, "rate iteration lost its iterate");
+        ISS_HIP(k_scale(x, 1.0 / r1, x, n, s));
+    }
+    ISS_HIP(hipStreamSynchronize(s));
+    return ISS_OK;
+}
+
 int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double* out, iss_stream_t stream) {
     if (!p || !a || !b || !out || n < 0) return fail(ISS_E_INVAL, "bad argument");
     hipStream_t s = (hipStream_t)stream;
@@ -1597,15 +1645,39 @@ int iss_net_create(iss_problem* p, iss_net** out) {
         delete net;
         return fail(ISS_E_HIP, std::string("net create: ") + hipGetErrorString(e));
     }
+    p->nets.push_back(net);
     *out = net;
     return ISS_OK;
 }
 
 void iss_net_destroy(iss_net* net) {
     if (!net) return;
-    if (net->p && net->p->net == net) net->p->net = nullptr;
+    if (net->p) {
+        if (net->p->net == net) net->p->net = nullptr;
+        auto& v = net->p->nets;
+        v.erase(std::remove(v.begin(), v.end(), net), v.end());
+    }
     net_destroy(net->impl);
     delete net;
+}
+
+int iss_net_save_input(iss_net* net, uint16_t* dst, iss_stream_t stream) {
+    if (!net || !dst) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_save_input(net->impl, dst, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_net_load_input(iss_net* net, const uint16_t* src, iss_stream_t stream) {
+    if (!net || !src) return fail(ISS_E_INVAL, "null argument");
+    ISS_HIP(net_load_input(net->impl, src, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_axpby(double a, const double* x, double b, double* y, int64_t n, iss_stream_t stream) {
+    if (!x || !y || n < 0) return fail(ISS_E_INVAL, "bad argument");
+    if (n == 0) return ISS_OK;
+    ISS_HIP(k_axpby(y, a, x, b, n, (hipStream_t)stream));
+    return ISS_OK;
 }
 
 int iss_net_info(const iss_net* net, int64_t* band_size, int64_t* num_params) {
@@ -1653,6 +1725,7 @@ int iss_net_backward(iss_net* net, const float* t, float* grad, double* loss, is
 
 int iss_net_correction(iss_net* net, double* c, iss_stream_t stream) {
     if (!net || !c) return fail(ISS_E_INVAL, "null argument");
+    if (!net->p) return fail(ISS_E_INVAL, "the problem of this network has been destroyed");
     const Level& L = net->p->lv[net->p->levels];
     ISS_HIP(net_output_correction(net->impl, c, (int64_t)(net->p->dim + 1) * L.v.N, (hipStream_t)stream));
     return ISS_OK;
@@ -1672,6 +1745,7 @@ int iss_adam_step(int64_t n, float* w, float* m, float* v, const float* g, float
 }
 
 int iss_problem_set_net(iss_problem* p, iss_net* net) {
+    if (net && !net->p) return fail(ISS_E_INVAL, "the problem of this network has been destroyed");
     if (!p) return fail(ISS_E_INVAL, "null problem");
     if (net && net->p != p) return fail(ISS_E_INVAL, "net belongs to another problem");
     p->net = net;

@@ -83,6 +83,9 @@ hipError_t k_convert(int prec_in, const void* in, int prec_out, void* out, int64
 // FP64), using `partial` (device, >= 1024 * nf doubles) as scratch.
 hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* partial,
                          double* out, hipStream_t s);
+// out[0] = sum of the n entries of x (partial: >= 1024 doubles); x -= sum / n
+hipError_t k_field_sum(const double* x, int64_t n, double* partial, double* out, hipStream_t s);
+hipError_t k_sub_mean(double* x, int64_t n, const double* sum, hipStream_t s);
 // out[i] = sum_e V_i[e] w[e] for i < k (V_i = V + i * ldv), and out[k] = w.w
 // if with_self; partial holds 65536 doubles.
 hipError_t k_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
@@ -135,5 +138,8 @@ hipError_t net_correction(NetImpl* n, const double* r, double* c, int64_t nvec, 
 hipError_t net_output_correction(NetImpl* n, double* c, int64_t nvec, hipStream_t s);
 hipError_t net_output_grad(NetImpl* n, const double* dldc, double factor, hipStream_t s);
 double* net_work(NetImpl* n, int which);
+// band rows of the network input (M x 8 BF16 bits) to / from caller memory
+hipError_t net_save_input(NetImpl* n, uint16_t* dst, hipStream_t s);
+hipError_t net_load_input(NetImpl* n, const uint16_t* src, hipStream_t s);
 
 }  // namespace iss

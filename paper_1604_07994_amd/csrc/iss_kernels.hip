@@ -919,21 +919,25 @@ __device__ __forceinline__ uint32_t sidx3(const LevelView& L, int i, int j, int 
            (uint32_t)(i >> 2);
 }
 
-// global loads of plane kk of NF fields (fields f0.. of the split vector xs)
-// for this thread's ZT_PER tile entries; entries past the lattice are 0
-template <int NF, typename T, typename C>
+// global loads of plane kk of NF fields (fields f0.. of the vector xs, in
+// the colour-split layout if SPLIT, else canonical) for this thread's
+// ZT_PER tile entries; entries past the lattice are 0
+template <int NF, bool SPLIT, typename T, typename C>
 __device__ __forceinline__ void ztile_fetch(const LevelView& L, const T* __restrict__ xs, int f0, int i0, int j0,
                                             int kk, C (&reg)[NF][ZT_PER]) {
+    const int64_t fstride = SPLIT ? L.Ns : L.N;
 #pragma unroll
     for (int q = 0; q < ZT_PER; ++q) {
         const int e = (int)threadIdx.x + 256 * q;
         const int r = e / ZT_W, c = e - r * ZT_W;
         const int ii = i0 - 1 + c, jj = j0 - 1 + r;
         const bool ok = e < ZT_A && ii <= L.n && jj <= L.n;
-        const uint32_t off = ok ? sidx3(L, ii, jj, kk) : 0u;
+        const uint32_t off = !ok ? 0u
+                             : SPLIT ? sidx3(L, ii, jj, kk)
+                                     : (uint32_t)kk * (uint32_t)L.sz + (uint32_t)jj * (uint32_t)L.sy + (uint32_t)ii;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const C v = (C)ld32(xs + (int64_t)(f0 + f) * L.Ns, off);
+            const C v = (C)ld32(xs + (int64_t)(f0 + f) * fstride, off);
             reg[f][q] = ok ? v : (C)0;
         }
     }
@@ -955,7 +959,7 @@ __device__ __forceinline__ void ztile_store(C (*lds)[3][ZT_A], int slot, const C
 // calls body(i, j, k, slot of k-1, slot of k, slot of k+1, active) for
 // every plane of the chunk (every thread of the workgroup takes part; the
 // body writes only if active).
-template <int NF, typename T, typename C, typename Body>
+template <int NF, bool SPLIT, typename T, typename C, typename Body>
 __device__ __forceinline__ void ztile_march(const LevelView& L, ZTileGrid zg, const T* __restrict__ xs, int f0,
                                             C (*lds)[3][ZT_A], Body&& body) {
     int i0, j0, k0, k1;
@@ -965,14 +969,14 @@ __device__ __forceinline__ void ztile_march(const LevelView& L, ZTileGrid zg, co
     const bool active = i <= L.n - 1 && j <= L.n - 1;
     C reg[NF][ZT_PER];
     for (int p = 0; p < 3; ++p) {
-        ztile_fetch<NF, T, C>(L, xs, f0, i0, j0, k0 - 1 + p, reg);
+        ztile_fetch<NF, SPLIT, T, C>(L, xs, f0, i0, j0, k0 - 1 + p, reg);
         ztile_store<NF, C>(lds, p, reg);
     }
     __syncthreads();
     int sm = 0, s0 = 1, sp = 2;
     for (int k = k0; k < k1; ++k) {
         const bool pre = k + 1 < k1;
-        if (pre) ztile_fetch<NF, T, C>(L, xs, f0, i0, j0, k + 2, reg);
+        if (pre) ztile_fetch<NF, SPLIT, T, C>(L, xs, f0, i0, j0, k + 2, reg);
         body(i, j, k, sm, s0, sp, active);
         __syncthreads();
         if (pre) ztile_store<NF, C>(lds, sm, reg);
@@ -995,7 +999,7 @@ __global__ __launch_bounds__(256) void k_p_rhs_z(LevelView L, ZTileGrid zg, cons
     const C sdv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
     const C vol = (C)kuhn_volume<D>();
     constexpr int c0 = sc_int<D>(0);
-    ztile_march<D + 1, T, C>(L, zg, xs, 0, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+    ztile_march<D + 1, true, T, C>(L, zg, xs, 0, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
         const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
         C dv = 0, cp = 0;
         static_for<0, KuhnTables<D>::NB>([&](auto oc) {
@@ -1030,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_vel_rhs_z(LevelView L, ZTileGrid zg, co
     constexpr int D = 3;
     __shared__ C lds[1][3][ZT_A];
     const C sbv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
-    ztile_march<1, T, C>(L, zg, xs, D, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+    ztile_march<1, true, T, C>(L, zg, xs, D, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
         const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
         C acc[D] = {0, 0, 0};
         static_for<0, KuhnTables<D>::NB>([&](auto oc) {
@@ -1053,6 +1057,80 @@ __global__ __launch_bounds__(256) void k_vel_rhs_z(LevelView L, ZTileGrid zg, co
 #pragma unroll
         for (int l = 0; l < D; ++l)
             g[(int64_t)l * L.Ns + v] = (T)((C)ld32(bs + (int64_t)l * L.Ns, v) - sbv * acc[l]);
+    });
+}
+
+// Operator apply / residual on the interior isoviscous vertices of a large
+// 3D level (canonical layout), as apply_bulk_body: the LDS z march with the
+// compile-time integer stencils of the Kuhn lattice (viscous block times
+// |T|, B and B^T times -|T|/(d+1), C times |T|).
+template <int F, int BLK, int MODE, typename T>
+__global__ __launch_bounds__(256) void k_apply_z(LevelView L, ZTileGrid zg, const T* __restrict__ x,
+                                                 const T* __restrict__ b, T* __restrict__ y) {
+    using C = typename Acc<T>::type;
+    constexpr int D = 3;
+    constexpr int NF = (BLK == BLOCK_FULL) ? D + 1 : D;
+    __shared__ C lds[NF][3][ZT_A];
+    const C vol = (C)kuhn_volume<D>();
+    const C bvol = (C)(-kuhn_volume<D>() / (D + 1));
+    ztile_march<NF, false, T, C>(L, zg, x, 0, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+        const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
+        C av[D] = {0, 0, 0}, bt[D] = {0, 0, 0}, dv = 0, cp = 0;
+        static_for<0, KuhnTables<D>::NB>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
+            const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+            const int e = cen + dy * ZT_W + dx;
+            static_for<0, D>([&](auto kc) {
+                constexpr int kk = decltype(kc)::value;
+                constexpr bool used = svis_int<D>(F, 0, kk, o) != 0 || svis_int<D>(F, 1, kk, o) != 0 ||
+                                      svis_int<D>(F, 2, kk, o) != 0 || (BLK == BLOCK_FULL && sdiv_int<D>(kk, o) != 0);
+                if constexpr (used) {
+                    const C u = lds[kk][slot][e];
+                    static_for<0, D>([&](auto lc) {
+                        constexpr int l = decltype(lc)::value;
+                        constexpr int wv = svis_int<D>(F, l, kk, o);
+                        if constexpr (wv != 0) av[l] += (C)wv * u;
+                    });
+                    if constexpr (BLK == BLOCK_FULL) {
+                        constexpr int wd = sdiv_int<D>(kk, o);
+                        if constexpr (wd != 0) dv += (C)wd * u;
+                    }
+                }
+            });
+            if constexpr (BLK == BLOCK_FULL) {
+                constexpr bool pused = sbt_int<D>(0, o) != 0 || sbt_int<D>(1, o) != 0 || sbt_int<D>(2, o) != 0 ||
+                                       sc_int<D>(o) != 0;
+                if constexpr (pused) {
+                    const C pv = lds[D][slot][e];
+                    static_for<0, D>([&](auto lc) {
+                        constexpr int l = decltype(lc)::value;
+                        constexpr int wb = sbt_int<D>(l, o);
+                        if constexpr (wb != 0) bt[l] += (C)wb * pv;
+                    });
+                    constexpr int wc = sc_int<D>(o);
+                    if constexpr (wc != 0) cp += (C)wc * pv;
+                }
+            }
+        });
+        if (!active) return;
+        const int64_t v = (int64_t)i + (int64_t)j * L.sy + (int64_t)k * L.sz;
+        const int ph = L.vphase[v];
+        if (ph == SPECIAL) return;
+        const C smu = PrecU<C>::mu(L, ph) * (C)L.sA * vol;
+        const C sb = (C)L.sB * bvol;
+        C out[D + 1];
+#pragma unroll
+        for (int l = 0; l < D; ++l) out[l] = smu * av[l] + (BLK == BLOCK_FULL ? sb * bt[l] : (C)0);
+        out[D] = (BLK == BLOCK_FULL) ? sb * dv - (C)L.sC * PrecU<C>::imu(L, ph) * (vol * cp) : (C)0;
+#pragma unroll
+        for (int f = 0; f <= D; ++f) {
+            const int64_t ef = (int64_t)f * L.N + v;
+            if (MODE == MODE_RESID)
+                y[ef] = (BLK == BLOCK_FULL || f < D) ? (T)((C)b[ef] - out[f]) : (T)0.0f;
+            else
+                y[ef] = (T)out[f];
+        }
     });
 }
 
@@ -1399,7 +1477,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
-template <typename T>
+template <typename T, bool SQUARE = true>
 __global__ __launch_bounds__(256) void k_sumsq_partial(const T* __restrict__ x, int64_t N,
                                                        int nf, double* __restrict__ partial) {
     __shared__ double sh[4];
@@ -1408,7 +1486,7 @@ __global__ __launch_bounds__(256) void k_sumsq_partial(const T* __restrict__ x, 
         const T* xf = x + (int64_t)f * N;
         for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
             const double t = (double)(typename Acc<T>::type)xf[e];
-            acc += t * t;
+            acc += SQUARE ? t * t : t;
         }
         const double s = block_sum<256>(acc, sh);
         if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = s;
@@ -1763,12 +1841,30 @@ hipError_t upload_tables(int dim, const void* t64, size_t bytes64, const void* t
 
 static inline int64_t special_blocks(int64_t ns, int wg = 256) { return (ns + wg - 1) / wg; }
 
+// host-side launch counter of the stencil kernels (iss_launch_counts)
+static inline void counted(const LevelView& L, int kind) {
+    if (L.launch_count) ++L.launch_count[kind];
+}
+
 template <int D, int F, int BLK, int MODE, typename T>
 static hipError_t apply_t(const LevelView& L, const T* x, const T* b, T* y, hipStream_t s) {
     const int64_t nb = interior_blocks<D>(L.n);
-    if (nb > 0)
+    if constexpr (D == 3) {
+        if (L.n > L.merge_max_n && L.n >= 2) {      // large levels: LDS z march
+            const ZTileGrid zg = ztile_grid(L.n);
+            hipLaunchKernelGGL((k_apply_z<F, BLK, MODE, T>), dim3((unsigned)(NXCD * zg.gx * zg.gys * zg.gz)), dim3(256),
+                               0, s, L, zg, x, b, y);
+            counted(L, ISS_L_APPLY_TILED);
+        } else if (nb > 0) {
+            hipLaunchKernelGGL((k_apply_bulk<D, F, BLK, MODE, T>), dim3((unsigned)nb), dim3(BX, BY), 0, s,
+                               L, x, b, y);
+            counted(L, ISS_L_APPLY_BULK);
+        }
+    } else if (nb > 0) {
         hipLaunchKernelGGL((k_apply_bulk<D, F, BLK, MODE, T>), dim3((unsigned)nb), dim3(BX, BY), 0, s,
                            L, x, b, y);
+        counted(L, ISS_L_APPLY_BULK);
+    }
     const int64_t ns = special_blocks(L.spec_off[D + 1]);
     if (ns > 0)
         hipLaunchKernelGGL((k_apply_special<D, F, BLK, MODE, T>), dim3((unsigned)ns), dim3(256), 0, s,
@@ -1798,10 +1894,6 @@ hipError_t k_apply(const LevelView& L, int form, int block, int mode, int prec, 
 
 static inline unsigned blocks256(int64_t threads) { return (unsigned)((threads + 255) / 256); }
 
-// host-side launch counter of the smoother kernels (iss_launch_counts)
-static inline void counted(const LevelView& L, int kind) {
-    if (L.launch_count) ++L.launch_count[kind];
-}
 
 // One Uzawa step (eq. Uzawa_smooth) on split-layout vectors: symmetric
 // velocity sweep (forward colours 0..d, backward d..0, the repeated colour d
@@ -2001,6 +2093,25 @@ hipError_t k_field_sumsq(int prec, const void* x, int64_t N, int nf, double* par
     ISS_BY_PREC(prec,
         hipLaunchKernelGGL((k_sumsq_partial<T>), dim3(nblk), dim3(256), 0, s, (const T*)x, N, nf, partial))
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, nf, out);
+    return hipGetLastError();
+}
+
+hipError_t k_field_sum(const double* x, int64_t N, double* partial, double* out, hipStream_t s) {
+    const int nblk = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (N + 255) / 256));
+    hipLaunchKernelGGL((k_sumsq_partial<double, false>), dim3(nblk), dim3(256), 0, s, x, N, 1, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nblk, 1, out);
+    return hipGetLastError();
+}
+
+// x -= sum[0] / n (sum on the device: no host round trip)
+__global__ __launch_bounds__(256) void k_sub_mean_t(double* __restrict__ x, int64_t n,
+                                                    const double* __restrict__ sum) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) x[e] -= sum[0] / (double)n;
+}
+
+hipError_t k_sub_mean(double* x, int64_t n, const double* sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_mean_t, grid1(n), dim3(256), 0, s, x, n, sum);
     return hipGetLastError();
 }
 

@@ -338,6 +338,19 @@ __global__ void k_zero(T* __restrict__ x, int64_t n) {
     if (e < n) x[e] = 0;
 }
 
+// band rows of the input activation (N x 8, BF16 bits) <-> compact M x 8
+template <bool SAVE>
+__global__ void k_band_rows(const int32_t* __restrict__ band, int64_t M, uint16_t* __restrict__ act0,
+                            uint16_t* __restrict__ compact) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * NET_CIN) return;
+    const int64_t m = e / NET_CIN;
+    const int c = (int)(e - m * NET_CIN);
+    const int64_t a = (int64_t)band[m] * NET_CIN + c;
+    if (SAVE) compact[e] = act0[a];
+    else act0[a] = compact[e];
+}
+
 }  // namespace iss
 
 // ===========================================================================
@@ -556,6 +569,18 @@ hipError_t net_correction(NetImpl* n, const double* r, double* c, int64_t nvec, 
     if ((e = net_forward(n, nullptr, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_zero<double>), dim3(nb256(nvec)), dim3(256), 0, s, c, nvec);
     hipLaunchKernelGGL(k_band_correct, dim3(nb256(n->g.M)), dim3(256), 0, s, n->g, n->y, n->scales, n->static_feat, c);
+    return hipGetLastError();
+}
+
+hipError_t net_save_input(NetImpl* n, uint16_t* dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_band_rows<true>), dim3(nb256(n->g.M * NET_CIN)), dim3(256), 0, s, n->band, n->g.M, n->act0,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t net_load_input(NetImpl* n, const uint16_t* src, hipStream_t s) {
+    hipLaunchKernelGGL((k_band_rows<false>), dim3(nb256(n->g.M * NET_CIN)), dim3(256), 0, s, n->band, n->g.M, n->act0,
+                       const_cast<uint16_t*>(src));
     return hipGetLastError();
 }
 

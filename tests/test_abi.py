@@ -47,7 +47,7 @@ def test_argument_validation_without_gpu():
     assert L.iss_default_options(ctypes.byref(opt)) == 0
     assert opt.nu1 == 3 and opt.nu2 == 3 and abs(opt.omega - 0.3) < 1e-15
     assert opt.coarse_form == -1 and opt.mid_form == -1
-    assert opt.merge_max_n == 64 and opt.spec_wide_min == 65536
+    assert opt.merge_max_n == 64 and opt.spec_wide_min == 65536 and opt.cycles == 1
 
 
 def _create(L, binding, dim=3, macro=1, levels=2, coarse=1, incs=(), mu=(1.0,), opt=None):
@@ -93,7 +93,7 @@ def test_problem_create_rejects_split_field_beyond_4gib():
 @pytest.mark.parametrize("field,value", [("nu1", -1), ("nu_inc", -2), ("restart", 0), ("outer", 5),
                                          ("coarse_mu", 7), ("coarse_form", 3), ("stab_beta", 0.0),
                                          ("mid_form", -2), ("mid_form", 3), ("merge_max_n", -1),
-                                         ("spec_wide_min", -1)])
+                                         ("spec_wide_min", -1), ("cycles", 0), ("cycles", 17)])
 def test_problem_create_rejects_bad_options(field, value):
     from paper_1604_07994_amd import binding
     L = binding.lib()

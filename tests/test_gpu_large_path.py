@@ -2,10 +2,11 @@
 
 On levels with n > 64 (129^3 and 257^3 in the benchmark) the Uzawa step of
 eq. Uzawa_smooth runs in separate bulk and special launches per colour
-phase: k_vel_rhs_s, k_gs_vel_s, k_gs_vel_special_s, the grouped pressure
-right-hand-side pass k_p_rhs_g (which also finishes colour 0), k_gs_p_s and
-k_gs_p_special_s in one-wave or 256-thread workgroups.  Smaller levels use
-merged launches.  The option merge_max_n = 0 selects the large-level
+phase: the right-hand-side passes (LDS-tiled in 3D: k_vel_rhs_z and
+k_p_rhs_z, which also finishes colour 0; k_vel_rhs_s and k_p_rhs_g in 2D),
+k_gs_vel_s, k_gs_vel_special_s, k_gs_p_s and k_gs_p_special_s in one-wave or
+256-thread workgroups; the bulk rows of applies and residuals take the
+LDS-tiled k_apply_z in 3D.  Smaller levels use merged launches.  The option merge_max_n = 0 selects the large-level
 kernels on every level and spec_wide_min = 0 sends every pressure special
 list to the 256-thread kernel, so these kernels are compared with the
 oracle here at sizes the oracle handles (17^3 to 33^3, 33^2, a ragged
@@ -64,6 +65,40 @@ def _check_large_launches(c, d, path, steps, form):
         assert c["gs_p_special_wide"] == m * steps and c["gs_p_special"] == 0, c
     else:
         assert c["gs_p_special"] == m * steps and c["gs_p_special_wide"] == 0, c
+
+
+@pytest.mark.parametrize("block", ["velocity", "full"])
+@pytest.mark.parametrize("form", ["gradient", "strain", "interface"])
+def test_apply_and_residual_large_path(case, form, block):
+    """Bulk rows of applies and residuals through the LDS-tiled kernel of
+    the large 3D levels (2D keeps one vertex per thread): K x and b - K x
+    against the assembled oracle operator, 1e-12 of max(|K| |x|)."""
+    import torch
+    from oracle import assemble
+    from tests.gpu_common import abs_scale, assert_close_scaled
+    w, P, path = case
+    D = assemble.Discretisation(w["dim"], w["n"], w["inclusions"], w["mu"])
+    K = D.stokes(form)
+    N = D.N
+    if block == "velocity":
+        K = K[:w["dim"] * N][:, :w["dim"] * N]
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=125)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=126)
+    if block == "full":
+        b[w["dim"] * N:] = iss_inputs.random_vector(w["dim"], w["n"], seed=127)[w["dim"] * N:]
+    xg, y = to_dev(x), torch.empty(x.size, dtype=torch.float64, device="cuda")
+    P.launch_counts(reset=True)
+    P.apply(form, xg, y, block=block)
+    c = P.launch_counts()
+    assert c["apply_tiled" if w["dim"] == 3 else "apply_bulk"] == 1, c
+    nv = K.shape[0]
+    ref = K @ x[:nv]
+    scale = abs_scale(K, x[:nv])
+    assert_close_scaled(to_host(y)[:nv], ref, scale, 1e-12, "%s/%s apply" % (form, block))
+    if block == "full":
+        r = torch.empty_like(y)
+        P.residual(form, xg, to_dev(b), r)
+        assert_close_scaled(to_host(r), b - K @ x, scale + np.abs(b), 1e-12, "%s residual" % form)
 
 
 @pytest.mark.parametrize("form", ["gradient", "strain", "interface"])

@@ -194,6 +194,47 @@ def test_fgmres_restart_cycles_match_oracle(restart):
     P.close()
 
 
+@pytest.mark.parametrize("cycles", [2, 3])
+def test_fgmres_multi_cycle_preconditioner_matches_oracle(cycles):
+    """Preconditioner = several stationary V-cycles from zero (the solve
+    option `cycles`): the FGMRES residual history follows the oracle's
+    FGMRES with the same preconditioner to 1e-6 (same well-conditioned case
+    as the restart tests)."""
+    import torch
+    w, b, H = _restart_case()
+    _, hist = mg.solve_fgmres(H, b, rtol=1e-11, restart=40, maxit=30, cycles=cycles)
+    P = gpu_problem(w, outer="fgmres", restart=40, nu1=2, nu2=2, cycles=cycles)
+    x = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
+    info = P.solve("interface", x, to_dev(b), rtol=1e-11, maxit=30, raise_on_fail=False)
+    g = np.array(info["history"])
+    k = min(len(g), len(hist))
+    assert k > 10 and abs(len(g) - len(hist)) <= 1, (len(g), len(hist))
+    assert np.allclose(g[:k], hist[:k], rtol=1e-6, atol=0), np.abs(g[:k] / hist[:k] - 1).max()
+    P.close()
+
+
+@pytest.mark.parametrize("name,levels,mu_in", [("square_split_2d", 5, 10.0), ("sphere_3d", 4, 10.0),
+                                               ("sphere_3d", 4, 1000.0)])
+def test_asymptotic_rate_matches_oracle(name, levels, mu_in):
+    """iss_asymptotic_rate (stationary V(3,3) cycles on K x = 0, rescaled
+    every cycle, Sec. 5) follows the oracle's rate history cycle by cycle
+    from the same start, for both forms; in the paper's regime (contrast
+    10) the cycle contracts (rate well below 1)."""
+    import torch
+    w = small_workload(name, levels)
+    w["mu"] = [1.0, mu_in]
+    x0 = iss_inputs.random_vector(w["dim"], w["n"], seed=36)
+    for form in ("interface", "strain"):
+        P = gpu_problem(w)
+        x = to_dev(x0)
+        g = np.array(P.asymptotic_rate(form, x, iters=25))
+        ref = _hier(w, form).rate_history(x0, 25)
+        assert np.allclose(g, ref, rtol=1e-7, atol=0), (form, np.abs(g / ref - 1).max())
+        if mu_in == 10.0:
+            assert g[-1] < 0.5, (form, g[-1])
+        P.close()
+
+
 def test_fgmres_2d_odd_length_matches_oracle():
     """2D FGMRES: 3 x 65^2 unknowns, an odd vector length, so the
     Gram-Schmidt kernels take their one-element-per-lane path; restart 17
