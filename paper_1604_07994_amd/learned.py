@@ -204,8 +204,23 @@ def main():
     ap.add_argument("--snapshots", type=int, default=10)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--stage", choices=["all", "train", "evaluate"], default="all",
+                    help="train: data and training only (writes the weights and the log); evaluate: the "
+                         "held-out comparison with the weights in --out, added to its log")
     args = ap.parse_args()
     log = lambda s: print(s, flush=True)
+    log_path = args.out.rsplit(".", 1)[0] + ".json"
+    test = list(range(100000, 100000 + args.test_seeds))
+    if args.stage == "evaluate":
+        weights = np.load(args.out, allow_pickle=False)["weights"]
+        with open(log_path) as f:
+            meta = json.load(f)
+        rows = evaluate(weights, test, args.levels, log=log)
+        meta.update({"test_seeds": test, "evaluation": rows, "summary": summarise(rows)})
+        with open(log_path, "w") as f:
+            json.dump(meta, f, indent=1)
+        log("summary " + json.dumps(meta["summary"]))
+        return
     nets, pairs, gen = generate(list(range(args.train_seeds)), args.levels, args.snapshots, log=log)
     log("training data: %s" % gen)
     vnets, vpairs, vgen = generate(list(range(1000, 1000 + args.val_seeds)), args.levels, args.snapshots, log=log)
@@ -213,17 +228,16 @@ def main():
     weights, meta = train(nets, pairs, vnets, vpairs, args.epochs, args.lr, log=log)
     for n_ in nets + vnets:
         n_.close()
-    test = list(range(100000, 100000 + args.test_seeds))
-    rows = evaluate(weights, test, args.levels, log=log)
-    summary = summarise(rows)
     meta.update({"levels": args.levels, "snapshots": args.snapshots, "training_data": gen,
                  "validation_data": vgen, "train_seeds": [0, args.train_seeds - 1],
-                 "validation_seeds": [1000, 1000 + args.val_seeds - 1], "test_seeds": test,
-                 "solver": SOLVER, "evaluation": rows, "summary": summary})
+                 "validation_seeds": [1000, 1000 + args.val_seeds - 1], "solver": SOLVER})
     np.savez(args.out, weights=weights)
-    with open(args.out.rsplit(".", 1)[0] + ".json", "w") as f:
+    if args.stage == "all":
+        rows = evaluate(weights, test, args.levels, log=log)
+        meta.update({"test_seeds": test, "evaluation": rows, "summary": summarise(rows)})
+        log("summary " + json.dumps(meta["summary"]))
+    with open(log_path, "w") as f:
         json.dump(meta, f, indent=1)
-    log("summary " + json.dumps(summary))
 
 
 if __name__ == "__main__":
