@@ -29,8 +29,11 @@
  *
  * Memory ownership.  Vector arguments are device pointers owned by the
  * caller (any allocator; 8-byte aligned).  The library allocates and owns
- * its metadata and internal work vectors (hipMalloc at create time, and
- * for the Krylov basis at the first solve); iss_problem_destroy frees them.
+ * its metadata (hipMalloc at create time) and the coarse factorisation.
+ * Its work vectors (per-level V-cycle and smoother buffers, the FGMRES
+ * basis) come from a workspace the caller binds with iss_bind_workspace,
+ * or, if none is bound, from hipMalloc at their first use; iss_problem_
+ * destroy frees what the library allocated.
  *
  * Streams.  Every call enqueues its kernels on the given stream and returns
  * without synchronising, except calls that return host scalars
@@ -61,7 +64,8 @@ enum iss_status {
     ISS_E_HIP = -2,       /* a HIP runtime call failed                      */
     ISS_E_NOTCONV = -3,   /* maxit reached before the tolerance; info set   */
     ISS_E_DIVERGED = -4,  /* residual grew by more than 1e3 or is NaN/Inf   */
-    ISS_E_NOMEM = -5      /* device or host allocation failed               */
+    ISS_E_NOMEM = -5,     /* device or host allocation failed               */
+    ISS_E_NOWS = -6       /* the bound workspace is too small               */
 };
 
 enum iss_form { ISS_GRADIENT = 0, ISS_STRAIN = 1, ISS_INTERFACE = 2 };
@@ -158,18 +162,53 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
                        const iss_inclusion* inclusions, int ninclusions,
                        const double* mu, int nphase, const iss_options* opt,
                        iss_problem** out);
+/* Same, with the viscosity given per fine element instead of by
+ * inclusions (any geometry; Sec. 5 writes the system for a general
+ * piecewise constant viscosity, the closing remark of Sec. 2.2 allows
+ * interfaces that the mesh does not resolve).  elem_phase (host, read
+ * during the call) holds one phase per element of the finest level,
+ * phase < nphase: element (cell c, type t) at index c * T + t with
+ * T = 6 (3D) or 2 (2D), cell c = ci + n (cj + n ck) for the cell with
+ * lowest corner (ci, cj, ck), n = macro 2^levels; type t is the position
+ * of the simplex's axis order in (x,y,z), (x,z,y), (y,x,z), (y,z,x),
+ * (z,x,y), (z,y,x) (2D: (x,y), (y,x)), the order in which its edges from
+ * the cell corner to the opposite corner step along the axes.  Coarse
+ * levels need ISS_COARSE_MU_AVERAGE (ISS_E_INVAL otherwise). */
+int iss_problem_create_elems(int dim, int macro, int levels, int coarse_level,
+                             const uint8_t* elem_phase, const double* mu, int nphase,
+                             const iss_options* opt, iss_problem** out);
 void iss_problem_destroy(iss_problem* p);
 
-/* Number of lattice vertices N of `level`; a vector has (dim+1) N entries. */
+/* Caller-owned workspace.  iss_workspace_bytes gives the bytes that every
+ * call of p in precision prec needs for its work buffers: the V-cycle and
+ * smoother vectors of every level in that precision, the FP64 FGMRES
+ * arrays for the restart length of the options (2 restart + 3 vectors of
+ * (dim+1) N doubles) and the two vectors of iss_asymptotic_rate, each
+ * rounded up to 256 bytes.  Calls in several precisions need the sum over
+ * those precisions.  iss_bind_workspace hands the library a device region
+ * (256-byte aligned) to take these buffers from instead of hipMalloc; it
+ * must come before the first call that needs a work buffer (ISS_E_INVAL
+ * otherwise), stays owned by the caller, and must stay allocated until
+ * iss_problem_destroy.  A call whose buffers no longer fit returns
+ * ISS_E_NOWS.  Sizes follow the unknowns of the system of Sec. 5 on every
+ * multigrid level. */
+int iss_workspace_bytes(const iss_problem* p, int prec, size_t* bytes);
+int iss_bind_workspace(iss_problem* p, void* dev_ptr, size_t bytes);
+
+/* Number of lattice vertices N of `level` (a uniformly refined level of
+ * the macro mesh, Sec. 2.2); a vector has (dim+1) N entries. */
 int iss_num_vertices(const iss_problem* p, int level, int64_t* n);
 
 /* Per-vertex class of `level` into host array cls (N bytes): bit 0 set for
- * interface vertices (incident element viscosities differ), bit 1 for
- * boundary vertices.  Counts go to *ninterface / *nboundary if non-NULL. */
+ * interface vertices (incident element viscosities differ: the vertices
+ * that keep the full a_tr rows in eq. equivalence-stencil, Sec. 2.2), bit 1
+ * for boundary vertices.  Counts go to *ninterface / *nboundary if non-NULL. */
 int iss_vertex_class(const iss_problem* p, int level, uint8_t* cls,
                      int64_t* ninterface, int64_t* nboundary);
 
-/* Buoyancy load b = (0, .., 0, -rho sum_{T in buoyant phases} |T|/(d+1), 0)
+/* Buoyancy load (the body force f of the Stokes problem of Sec. 1, eq. weaks
+ * tested with the P1 basis): b = (0, .., 0, -rho sum_{T in buoyant phases}
+ * |T|/(d+1), 0)
  * (body force (0,..,0,-rho) on elements of the listed phases) at `level`
  * into device FP64 vector b (overwritten).  With ISS_COARSE_MU_AVERAGE only
  * the finest level carries the problem's phases (ISS_E_INVAL otherwise). */
@@ -177,14 +216,18 @@ int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
                      double rho, double* b, iss_stream_t stream);
 
 /* y = K x (block ISS_FULL_STOKES) or y = (A x_u, 0) (ISS_VELOCITY_ONLY) at
- * `level` with the viscous form `form`.  prec selects the element type of
- * x and y (double / float); accumulation in that type. */
+ * `level` with the viscous form `form`: the saddle-point operator of the
+ * system of Sec. 5 with A from eq. standard (strain), eq. newbil applied
+ * as eq. equivalence-stencil (interface) or the gradient form of Sec. 1.
+ * prec selects the element type of x and y (double, float, BF16 storage
+ * with FP32 arithmetic); accumulation in the arithmetic type. */
 int iss_apply(iss_problem* p, int form, int block, int level, int prec,
               const void* x, void* y, iss_stream_t stream);
 
-/* r = b - K x at `level`.  If norms is non-NULL it receives d+2 FP64
- * numbers: the Euclidean norm of each field of r and of all of r (the
- * call then synchronises). */
+/* r = b - K x at `level`, the residual of the system of Sec. 5 that the
+ * multigrid cycle restricts and the solve monitors.  If norms is non-NULL
+ * it receives d+2 FP64 numbers: the Euclidean norm of each field of r and
+ * of all of r (the call then synchronises). */
 int iss_residual(iss_problem* p, int form, int level, int prec, const void* x,
                  const void* b, void* r, double* norms, iss_stream_t stream);
 
@@ -226,20 +269,24 @@ int iss_smooth_noalloc(iss_problem* p, int form, int level, int prec, int nsteps
 int iss_smooth_timed(iss_problem* p, int form, int level, int prec, int nsteps,
                      void* x, const void* b, iss_stream_t stream, double* ms);
 
-/* Grid transfers between `level` (fine) and level-1: restriction
- * rc = P^T rf (velocity zero on coarse boundary vertices) and
- * xf += P ec, P = P1 interpolation between the nested lattices. */
+/* Grid transfers between `level` (fine) and level-1, the standard
+ * transfers of the multigrid method of Sec. 5: restriction rc = P^T rf
+ * (velocity zero on coarse boundary vertices) and xf += P ec, P = P1
+ * interpolation between the nested lattices. */
 int iss_restrict(iss_problem* p, int level, int prec, const void* rf, void* rc,
                  iss_stream_t stream);
 int iss_prolong_add(iss_problem* p, int level, int prec, const void* ec, void* xf,
                     iss_stream_t stream);
 
-/* Direct solve on the coarsest level: x = K_c^+ b with sum_j w_j p_j = 0,
- * w_j = int mu^{-1} lambda_j (the space Q of Sec. 1).  FP64 always. */
+/* Direct solve on the coarsest level (Sec. 5 allows a direct coarse
+ * solver): x = K_c^+ b with sum_j w_j p_j = 0, w_j = int mu^{-1} lambda_j
+ * (the space Q of Sec. 1).  FP64 always. */
 int iss_coarse_solve(iss_problem* p, int form, const double* b, double* x,
                      iss_stream_t stream);
 
-/* One V(nu1, nu2) cycle on the finest level, in place on x.
+/* One V(nu1, nu2) cycle of the all-at-once Uzawa multigrid of Sec. 5
+ * (smoother eq. Uzawa_smooth, standard transfers, direct coarsest solve)
+ * on the finest level, in place on x.
  *
  * The part of the cycle below the finest level works only on the
  * library's own per-level buffers.  Its first run for a (coarse form,
@@ -254,10 +301,12 @@ int iss_coarse_solve(iss_problem* p, int form, const double* b, double* x,
 int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b,
                iss_stream_t stream);
 
-/* Solve K x = b on the finest level to ||b - K x|| <= rtol ||b|| from the
+/* Solve K x = b (the system of Sec. 5) on the finest level to
+ * ||b - K x|| <= rtol ||b|| (the residual reduction of Sec. 5) from the
  * initial guess in x (FP64 vectors).  The outer iteration (options) is
- * Richardson with one V-cycle per step, or right-preconditioned FGMRES
- * with one V-cycle as preconditioner.  prec = ISS_FP32 runs the V-cycle
+ * Richardson with V-cycles (the stationary iteration of Sec. 5), or
+ * right-preconditioned FGMRES (Saad 1993) with `cycles` stationary
+ * V-cycles from zero as preconditioner.  prec = ISS_FP32 runs the V-cycle
  * (stencil applies, smoothers, transfers) in FP32 while the outer
  * residual, orthogonalisation, solution update and the coarsest solve
  * stay FP64; ISS_FP32_BF16STORE does the same with the V-cycle's vectors
@@ -282,7 +331,8 @@ int iss_asymptotic_rate(iss_problem* p, int form, int iters, double* x, double* 
  * callers that drive the solver pieces themselves). */
 int iss_axpby(double a, const double* x, double b, double* y, int64_t n, iss_stream_t stream);
 
-/* Euclidean dot product of two FP64 device vectors of length n. */
+/* Euclidean dot product of two FP64 device vectors of length n (the inner
+ * products of the outer Krylov iteration). */
 int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double* out,
             iss_stream_t stream);
 

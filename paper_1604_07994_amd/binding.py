@@ -59,7 +59,7 @@ EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "
            "iss_net_targets", "iss_net_backward", "iss_adam_step", "iss_problem_set_net",
            "iss_net_correction", "iss_net_output_grad", "iss_smooth_timed", "iss_launch_counts",
            "iss_smooth_noalloc", "iss_asymptotic_rate", "iss_net_save_input", "iss_net_load_input",
-           "iss_axpby"]
+           "iss_axpby", "iss_problem_create_elems", "iss_workspace_bytes", "iss_bind_workspace"]
 
 
 def lib():
@@ -115,6 +115,10 @@ def lib():
     L.iss_net_save_input.argtypes = [vp, vp, vp]
     L.iss_net_load_input.argtypes = [vp, vp, vp]
     L.iss_axpby.argtypes = [cdbl, vp, cdbl, vp, i64, vp]
+    L.iss_problem_create_elems.argtypes = [cint, cint, cint, cint, vp, ctypes.POINTER(cdbl), cint,
+                                           ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.iss_workspace_bytes.argtypes = [vp, cint, ctypes.POINTER(ctypes.c_size_t)]
+    L.iss_bind_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     _lib = L
     return L
 
@@ -160,27 +164,54 @@ class Problem:
 
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
-                 coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536, cycles=1):
+                 coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536, cycles=1,
+                 elem_phase=None):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
                       -1 if coarse_form is None else FORMS[coarse_form], nu_inc,
                       -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min, cycles)
-        incs = inclusions_to_c(inclusions)
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()
-        _check(L.iss_problem_create(dim, macro, levels, coarse, incs, len(inclusions), mu_arr,
-                                    len(mu), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = None
+        if elem_phase is not None:
+            ph = np.ascontiguousarray(elem_phase, dtype=np.uint8)
+            _check(L.iss_problem_create_elems(dim, macro, levels, coarse, ph.ctypes.data_as(ctypes.c_void_p),
+                                              mu_arr, len(mu), ctypes.byref(opt), ctypes.byref(h)))
+        else:
+            incs = inclusions_to_c(inclusions)
+            _check(L.iss_problem_create(dim, macro, levels, coarse, incs, len(inclusions), mu_arr,
+                                        len(mu), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
 
     @classmethod
     def from_workload(cls, w, **kw):
         return cls(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"], **kw)
 
+    @classmethod
+    def from_elems(cls, dim, macro, levels, coarse, elem_phase, mu, **kw):
+        """Problem with one phase per finest-level element (library element
+        order, see iss_problem_create_elems)."""
+        kw.setdefault("coarse_mu", "average")
+        return cls(dim, macro, levels, coarse, [], mu, elem_phase=elem_phase, **kw)
+
+    def workspace_bytes(self, prec="fp64"):
+        out = ctypes.c_size_t()
+        _check(lib().iss_workspace_bytes(self._h, {"fp64": PREC_F64, "fp32": PREC_F32, "bf16": PREC_BF16}[prec],
+                                         ctypes.byref(out)))
+        return out.value
+
+    def bind_workspace(self, buf):
+        """Take every work buffer from the caller's device tensor buf (kept
+        referenced here until close)."""
+        _check(lib().iss_bind_workspace(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        self._workspace = buf
+
     def close(self):
         if getattr(self, "_h", None):
             lib().iss_problem_destroy(self._h)
             self._h = None
+        self._workspace = None
 
     def __del__(self):
         try:

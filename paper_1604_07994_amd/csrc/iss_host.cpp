@@ -258,6 +258,11 @@ struct iss_problem {
     VGraph vgraph[3][3];
     hipStream_t cap_stream = nullptr;
     int64_t launch_count[ISS_L_KINDS] = {};   // smoother launches per kernel shape
+    // caller-owned workspace (iss_bind_workspace): work vectors, the Krylov
+    // arrays and the rate buffers are carved from it instead of hipMalloc
+    char* ws_base = nullptr;
+    size_t ws_size = 0, ws_used = 0;
+    std::vector<uint8_t> elem_in;   // per-element phases given at creation (finest level)
     int device = 0;                 // HIP device current at creation
     void* scratch_dev = nullptr;    // that device's address of `scratch`
     std::vector<void*> allocs;
@@ -300,6 +305,23 @@ int dev_alloc(iss_problem* p, void** ptr, size_t bytes) {
     return ISS_OK;
 }
 
+// Work buffers: from the bound workspace if there is one (256-byte
+// aligned bump allocation), else hipMalloc.
+constexpr size_t WS_ALIGN = 256;
+inline size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) & ~(WS_ALIGN - 1); }
+
+int work_alloc(iss_problem* p, void** ptr, size_t bytes) {
+    if (!p->ws_base) return dev_alloc(p, ptr, bytes);
+    *ptr = nullptr;
+    const size_t need = ws_round(std::max<size_t>(bytes, 8));
+    if (p->ws_used + need > p->ws_size)
+        return fail(ISS_E_NOWS, "workspace too small: " + std::to_string(p->ws_used + need) + " bytes needed, " +
+                                    std::to_string(p->ws_size) + " bound");
+    *ptr = p->ws_base + p->ws_used;
+    p->ws_used += need;
+    return ISS_OK;
+}
+
 template <typename T>
 int dev_upload(iss_problem* p, T** ptr, const T* host, size_t count) {
     int rc = dev_alloc(p, (void**)ptr, count * sizeof(T));
@@ -333,8 +355,13 @@ void centroid_phases(iss_problem* p, int l) {
     const int n = p->macro << l;
     const int64_t ncell = (D == 3) ? (int64_t)n * n * n : (int64_t)n * n;
     L.elem_phase.assign(ncell * NT, 0);
-#pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < ncell; ++c) {
+    const bool given = l == p->levels && !p->elem_in.empty();
+    if (given) {
+        L.elem_phase = p->elem_in;                // phases given per element
+        std::vector<uint8_t>().swap(p->elem_in);
+    }
+#pragma omp parallel for schedule(static) if (!given)
+    for (int64_t c = 0; c < (given ? 0 : ncell); ++c) {
         const int ci = (int)(c % n), cj = (int)((c / n) % n), ck = (D == 3) ? (int)(c / ((int64_t)n * n)) : 0;
         for (int ty = 0; ty < NT; ++ty) {
             double cen[3] = {0, 0, 0};
@@ -637,11 +664,11 @@ int ensure_work(iss_problem* p, int l, int prec) {
     if (L.w_x[prec]) return ISS_OK;
     const size_t bytes = (size_t)(p->dim + 1) * L.v.N * prec_bytes(prec);
     int rc;
-    if ((rc = dev_alloc(p, &L.w_x[prec], bytes))) return rc;
-    if ((rc = dev_alloc(p, &L.w_b[prec], bytes))) return rc;
-    if ((rc = dev_alloc(p, &L.w_r[prec], bytes))) return rc;
+    if ((rc = work_alloc(p, &L.w_x[prec], bytes))) return rc;
+    if ((rc = work_alloc(p, &L.w_b[prec], bytes))) return rc;
+    if ((rc = work_alloc(p, &L.w_r[prec], bytes))) return rc;
     const size_t sbytes = (size_t)3 * (p->dim + 1) * L.v.Ns * prec_bytes(prec);
-    if ((rc = dev_alloc(p, &L.w_s[prec], sbytes))) return rc;
+    if ((rc = work_alloc(p, &L.w_s[prec], sbytes))) return rc;
     return ISS_OK;
 }
 
@@ -972,6 +999,7 @@ int precondition(iss_problem* p, int form, int prec, const double* v, double* z,
 int ensure_krylov(iss_problem* p, int m) {
     if (p->kry_m >= m && p->d_V) return ISS_OK;
     if (2 * m + 4 > 8192) return fail(ISS_E_INVAL, "restart length too large");
+    if (p->d_V && p->ws_base) return fail(ISS_E_NOWS, "Krylov arrays of another restart length in a bound workspace");
     if (p->d_V) {
         (void)hipFree(p->d_V); (void)hipFree(p->d_Z); (void)hipFree(p->d_w); (void)hipFree(p->d_r); (void)hipFree(p->d_h);
         auto rm = [&](void* q) { p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), q), p->allocs.end()); };
@@ -979,11 +1007,11 @@ int ensure_krylov(iss_problem* p, int m) {
     }
     const int64_t n = (int64_t)(p->dim + 1) * p->lv[p->levels].v.N;
     int rc;
-    if ((rc = dev_alloc(p, (void**)&p->d_V, (size_t)(m + 1) * n * 8))) return rc;
-    if ((rc = dev_alloc(p, (void**)&p->d_Z, (size_t)m * n * 8))) return rc;
-    if ((rc = dev_alloc(p, (void**)&p->d_w, (size_t)n * 8))) return rc;
-    if ((rc = dev_alloc(p, (void**)&p->d_r, (size_t)n * 8))) return rc;
-    if ((rc = dev_alloc(p, (void**)&p->d_h, (size_t)(2 * m + 4) * 8))) return rc;
+    if ((rc = work_alloc(p, (void**)&p->d_V, (size_t)(m + 1) * n * 8))) return rc;
+    if ((rc = work_alloc(p, (void**)&p->d_Z, (size_t)m * n * 8))) return rc;
+    if ((rc = work_alloc(p, (void**)&p->d_w, (size_t)n * 8))) return rc;
+    if ((rc = work_alloc(p, (void**)&p->d_r, (size_t)n * 8))) return rc;
+    if ((rc = work_alloc(p, (void**)&p->d_h, (size_t)(2 * m + 4) * 8))) return rc;
     p->kry_m = m;
     return ISS_OK;
 }
@@ -1205,8 +1233,24 @@ void iss_problem_destroy(iss_problem* p) {
     delete p;
 }
 
+static int create_impl(int dim, int macro, int levels, int coarse_level, const iss_inclusion* inclusions,
+                       int ninclusions, const uint8_t* elem_phase, const double* mu, int nphase,
+                       const iss_options* opt, iss_problem** out);
+
 int iss_problem_create(int dim, int macro, int levels, int coarse_level,
                        const iss_inclusion* inclusions, int ninclusions, const double* mu, int nphase,
+                       const iss_options* opt, iss_problem** out) {
+    return create_impl(dim, macro, levels, coarse_level, inclusions, ninclusions, nullptr, mu, nphase, opt, out);
+}
+
+int iss_problem_create_elems(int dim, int macro, int levels, int coarse_level, const uint8_t* elem_phase,
+                             const double* mu, int nphase, const iss_options* opt, iss_problem** out) {
+    if (!elem_phase) return fail(ISS_E_INVAL, "null element phases");
+    return create_impl(dim, macro, levels, coarse_level, nullptr, 0, elem_phase, mu, nphase, opt, out);
+}
+
+static int create_impl(int dim, int macro, int levels, int coarse_level, const iss_inclusion* inclusions,
+                       int ninclusions, const uint8_t* elem_phase, const double* mu, int nphase,
                        const iss_options* opt, iss_problem** out) {
     if (!out) return fail(ISS_E_INVAL, "null out");
     *out = nullptr;
@@ -1246,6 +1290,19 @@ int iss_problem_create(int dim, int macro, int levels, int coarse_level,
     p->mu.resize(256, 1.0);
     if (opt) p->opt = *opt;
     else iss_default_options(&p->opt);
+    if (elem_phase) {
+        const int64_t ne = (dim == 3 ? n * n * n * 6 : n * n * 2);
+        for (int64_t e = 0; e < ne; ++e)
+            if (elem_phase[e] >= nphase) {
+                delete p;
+                return fail(ISS_E_INVAL, "element phase out of range");
+            }
+        if (p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) {
+            delete p;
+            return fail(ISS_E_INVAL, "per-element phases need ISS_COARSE_MU_AVERAGE (no geometry to rediscretise)");
+        }
+        p->elem_in.assign(elem_phase, elem_phase + ne);
+    }
     {
         const char* g = std::getenv("ISS_VCYCLE_GRAPH");
         p->use_graphs = !(g && std::strcmp(g, "0") == 0);
@@ -1544,7 +1601,7 @@ int iss_asymptotic_rate(iss_problem* p, int form, int iters, double* x, double* 
     const int64_t N = L.v.N, n = (int64_t)(D + 1) * N;
     const hipStream_t s = (hipStream_t)stream;
     if (!p->d_rate) {
-        if ((rc = dev_alloc(p, (void**)&p->d_rate, (size_t)2 * n * sizeof(double)))) return rc;
+        if ((rc = work_alloc(p, (void**)&p->d_rate, (size_t)2 * n * sizeof(double)))) return rc;
         ISS_HIP(k_fill(PREC_F64, p->d_rate, n, 0.0, s));
     }
     const double* zero = p->d_rate;
@@ -1580,6 +1637,38 @@ int iss_dot(iss_problem* p, const double* a, const double* b, int64_t n, double*
     ISS_HIP(hipMemcpyAsync(p->h_pinned, p->d_red, sizeof(double), hipMemcpyDeviceToHost, s));
     ISS_HIP(hipStreamSynchronize(s));
     *out = p->h_pinned[0];
+    return ISS_OK;
+}
+
+int iss_workspace_bytes(const iss_problem* p, int prec, size_t* bytes) {
+    if (!p || !bytes) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    const int nf = p->dim + 1;
+    size_t t = 0;
+    for (int l = p->coarse; l <= p->levels; ++l) {       // work vectors of every level
+        const LevelView& V = p->lv[l].v;
+        t += 3 * ws_round((size_t)nf * V.N * prec_bytes(prec));
+        t += ws_round((size_t)3 * nf * V.Ns * prec_bytes(prec));
+    }
+    const size_t n = (size_t)nf * p->lv[p->levels].v.N;
+    const size_t m = (size_t)std::max(1, p->opt.restart);
+    t += ws_round((m + 1) * n * 8) + ws_round(m * n * 8) + 2 * ws_round(n * 8) + ws_round((2 * m + 4) * 8);
+    t += ws_round(2 * n * 8);                              // rate measurement
+    *bytes = t;
+    return ISS_OK;
+}
+
+int iss_bind_workspace(iss_problem* p, void* dev_ptr, size_t bytes) {
+    if (!p || !dev_ptr) return fail(ISS_E_INVAL, "null argument");
+    if (((uintptr_t)dev_ptr & (WS_ALIGN - 1)) != 0) return fail(ISS_E_INVAL, "workspace must be 256-byte aligned");
+    bool used = p->d_V || p->d_rate || p->ws_base;
+    for (const auto& L : p->lv)
+        for (int q = 0; q < 3; ++q) used = used || L.w_x[q] || L.w_s[q];
+    if (used) return fail(ISS_E_INVAL, "bind the workspace before the first call that needs work buffers");
+    p->ws_base = (char*)dev_ptr;
+    p->ws_size = bytes;
+    p->ws_used = 0;
     return ISS_OK;
 }
 
