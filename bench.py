@@ -242,7 +242,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         fp32 = {}
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16", "fp16"):
             x.zero_()
             P.solve(forms[0], x, b, prec=prec, rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
             x.zero_()

@@ -25,7 +25,8 @@
  * Dirichlet values: inputs must hold 0 there and outputs hold 0 there.
  * Pressure lives on every vertex.  Element type: double for ISS_FP64,
  * float for ISS_FP32, bfloat16 (1-8-7 bits, round to nearest even) for
- * ISS_FP32_BF16STORE, whose arithmetic is FP32 (see each call).
+ * ISS_FP32_BF16STORE and IEEE half (1-5-10 bits) for ISS_FP32_FP16STORE,
+ * both with FP32 arithmetic (see each call).
  *
  * Memory ownership.  Vector arguments are device pointers owned by the
  * caller (any allocator; 8-byte aligned).  The library allocates and owns
@@ -70,7 +71,7 @@ enum iss_status {
 
 enum iss_form { ISS_GRADIENT = 0, ISS_STRAIN = 1, ISS_INTERFACE = 2 };
 enum iss_block { ISS_VELOCITY_ONLY = 0, ISS_FULL_STOKES = 1 };
-enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1, ISS_FP32_BF16STORE = 2 };
+enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1, ISS_FP32_BF16STORE = 2, ISS_FP32_FP16STORE = 3 };
 enum iss_outer { ISS_OUTER_RICHARDSON = 0, ISS_OUTER_FGMRES = 1 };
 enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1 };
 enum iss_coarse_mu { ISS_COARSE_MU_CENTROID = 0, ISS_COARSE_MU_AVERAGE = 1 };
@@ -135,6 +136,11 @@ typedef struct {
                            * iss_solve: z = the iterate after `cycles` steps
                            * of the stationary V-cycle iteration on K z = r
                            * from z = 0 (default 1). */
+    double f16_rms;       /* ISS_FP32_FP16STORE: RMS the scaled input of
+                           * the FP16 V-cycle is normalised to (default
+                           * 2^-10: the cycle's corrections exceed its input
+                           * by up to the inverse of the smallest eigenvalue,
+                           * and FP16 ends at 65504). */
 } iss_options;
 
 typedef struct {
@@ -310,7 +316,13 @@ int iss_vcycle(iss_problem* p, int form, int prec, void* x, const void* b,
  * (stencil applies, smoothers, transfers) in FP32 while the outer
  * residual, orthogonalisation, solution update and the coarsest solve
  * stay FP64; ISS_FP32_BF16STORE does the same with the V-cycle's vectors
- * stored in BF16.  info may be NULL. */
+ * stored in BF16, ISS_FP32_FP16STORE with them stored in FP16: FP16 has
+ * five exponent bits, so that V-cycle runs on the symmetrically scaled
+ * system (S K S) y = gamma S v, S = diag(sig_u on velocity, sig_p on
+ * pressure) chosen at creation to make the isoviscous diagonal one for the
+ * viscosity sqrt(mu_min mu_max), gamma making the RMS of gamma S v the
+ * option f16_rms, and the preconditioned vector is S y / gamma.  info may
+ * be NULL. */
 int iss_solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
               const double* b, iss_solve_info* info, iss_stream_t stream);
 

@@ -18,6 +18,8 @@ OUTER = {"richardson": 0, "fgmres": 1}
 COARSE_MU = {"centroid": 0, "average": 1}
 PREC_F64, PREC_F32 = 0, 1
 PREC_BF16 = 2            # vectors stored in BF16, arithmetic in FP32
+PREC_F16 = 3             # vectors stored in FP16, arithmetic in FP32
+PRECS = {"fp64": PREC_F64, "fp32": PREC_F32, "bf16": PREC_BF16, "fp16": PREC_F16}
 
 _lib = None
 
@@ -35,7 +37,7 @@ class Options(ctypes.Structure):
                 ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int),
                 ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int),
                 ("mid_form", ctypes.c_int), ("merge_max_n", ctypes.c_int), ("spec_wide_min", ctypes.c_int),
-                ("cycles", ctypes.c_int)]
+                ("cycles", ctypes.c_int), ("f16_rms", ctypes.c_double)]
 
 
 # iss_launch_kind: smoother kernel shapes counted by iss_launch_counts
@@ -141,7 +143,9 @@ def _prec(t):
         return PREC_F32
     if t.dtype == torch.bfloat16:
         return PREC_BF16
-    raise ValueError("vectors must be float64, float32 or bfloat16")
+    if t.dtype == torch.float16:
+        return PREC_F16
+    raise ValueError("vectors must be float64, float32, bfloat16 or float16")
 
 
 def inclusions_to_c(inclusions):
@@ -165,12 +169,12 @@ class Problem:
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
                  coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536, cycles=1,
-                 elem_phase=None):
+                 f16_rms=1.0 / 1024.0, elem_phase=None):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
                       -1 if coarse_form is None else FORMS[coarse_form], nu_inc,
-                      -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min, cycles)
+                      -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min, cycles, f16_rms)
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()
         self._h = None
@@ -197,7 +201,7 @@ class Problem:
 
     def workspace_bytes(self, prec="fp64"):
         out = ctypes.c_size_t()
-        _check(lib().iss_workspace_bytes(self._h, {"fp64": PREC_F64, "fp32": PREC_F32, "bf16": PREC_BF16}[prec],
+        _check(lib().iss_workspace_bytes(self._h, PRECS[prec],
                                          ctypes.byref(out)))
         return out.value
 
@@ -321,7 +325,7 @@ class Problem:
         import torch
         hist = (ctypes.c_double * (maxit + 1))()
         info = SolveInfo(0, 0.0, 0.0, 0, ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), 0, 0)
-        rc = lib().iss_solve(self._h, FORMS[form], {"fp64": PREC_F64, "fp32": PREC_F32, "bf16": PREC_BF16}[prec], rtol,
+        rc = lib().iss_solve(self._h, FORMS[form], PRECS[prec], rtol,
                              maxit, self._vec(x, self.levels, torch.float64),
                              self._vec(b, self.levels, torch.float64), ctypes.byref(info), _stream())
         if rc != 0 and raise_on_fail:

@@ -182,6 +182,7 @@ struct DevBuf {
 
 struct Level {
     LevelView v{};
+    LevelView v16{};                // the same level for the scaled FP16 V-cycle (S K S)
     uint8_t* d_vphase = nullptr;
     uint8_t* d_vphase_s = nullptr;  // phase bytes in the colour-split layout
     int32_t* d_spec = nullptr;
@@ -198,10 +199,11 @@ struct Level {
     float* d_mu32 = nullptr;
     float* d_imu32 = nullptr;
     int64_t ninterface = 0, nboundary = 0;
-    void* w_x[3] = {nullptr, nullptr, nullptr};
-    void* w_b[3] = {nullptr, nullptr, nullptr};
-    void* w_r[3] = {nullptr, nullptr, nullptr};
-    void* w_s[3] = {nullptr, nullptr, nullptr};   // split layout: xs, bs, ws (d+1 fields each)
+    // work vectors per storage precision (PREC_F64 .. PREC_F16)
+    void* w_x[NPREC] = {};
+    void* w_b[NPREC] = {};
+    void* w_r[NPREC] = {};
+    void* w_s[NPREC] = {};   // split layout: xs, bs, ws (d+1 fields each)
 };
 
 struct Coarse {
@@ -255,7 +257,7 @@ struct iss_problem {
     // coarse part of the V-cycle per (form, precision) as a HIP graph;
     // ISS_VCYCLE_GRAPH=0 in the environment at creation turns it off
     bool use_graphs = true;
-    VGraph vgraph[3][3];
+    VGraph vgraph[3][NPREC];
     hipStream_t cap_stream = nullptr;
     int64_t launch_count[ISS_L_KINDS] = {};   // smoother launches per kernel shape
     // caller-owned workspace (iss_bind_workspace): work vectors, the Krylov
@@ -263,6 +265,12 @@ struct iss_problem {
     char* ws_base = nullptr;
     size_t ws_size = 0, ws_used = 0;
     std::vector<uint8_t> elem_in;   // per-element phases given at creation (finest level)
+    // scaled FP16 V-cycle: K~ = S K S with S = diag(sig_u on velocity,
+    // sig_p on pressure); f16_scaled marks the V-cycles run on K~
+    double sig_u = 1.0, sig_p = 1.0;
+    bool f16_scaled = false;
+    double* d_f16mul = nullptr;     // [gamma sig_f | sig_f / gamma] of the current input
+    int nphase = 1;
     int device = 0;                 // HIP device current at creation
     void* scratch_dev = nullptr;    // that device's address of `scratch`
     std::vector<void*> allocs;
@@ -834,7 +842,13 @@ int ensure_coarse(iss_problem* p, int form) {
 // multigrid
 
 int check_form(int form) { return (form >= 0 && form <= 2) ? ISS_OK : fail(ISS_E_INVAL, "bad form"); }
-int check_prec(int prec) { return (prec >= 0 && prec <= 2) ? ISS_OK : fail(ISS_E_INVAL, "bad precision"); }
+int check_prec(int prec) { return (prec >= 0 && prec < NPREC) ? ISS_OK : fail(ISS_E_INVAL, "bad precision"); }
+
+// the view of level l a V-cycle in precision prec works with: the scaled
+// system inside the FP16 preconditioner, else the level itself
+const LevelView& view(const iss_problem* p, int l, int prec) {
+    return (prec == PREC_F16 && p->f16_scaled) ? p->lv[l].v16 : p->lv[l].v;
+}
 int check_level(const iss_problem* p, int l) {
     return (l >= p->coarse && l <= p->levels) ? ISS_OK : fail(ISS_E_INVAL, "level out of range");
 }
@@ -856,10 +870,17 @@ int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hip
     Coarse& cs = p->cs;
     const Level& L = p->lv[p->coarse];
     const int64_t m = cs.M - 1;
-    ISS_HIP(k_gather(prec, b, cs.d_free, m, cs.d_bc, s));
+    // on the scaled system S K S: x~ = S^-1 K^-1 S^-1 b~ (field multipliers)
+    FieldMul fm{};
+    if (prec == PREC_F16 && p->f16_scaled) {
+        for (int f = 0; f <= p->dim; ++f) fm.m[f] = 1.0 / (f < p->dim ? p->sig_u : p->sig_p);
+        fm.N = L.v.N;
+        fm.on = 1;
+    }
+    ISS_HIP(k_gather(prec, b, cs.d_free, m, cs.d_bc, s, fm));
     ISS_HIP(k_dense_matvec(cs.d_Kinv[form], cs.M, cs.d_bc, cs.d_xc, s));
     ISS_HIP(k_fill(prec, x, (int64_t)(p->dim + 1) * L.v.N, 0.0, s));
-    ISS_HIP(k_scatter(prec, cs.d_xc, cs.d_free, m, x, s));
+    ISS_HIP(k_scatter(prec, cs.d_xc, cs.d_free, m, x, s, fm));
     return ISS_OK;
 }
 
@@ -878,7 +899,9 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bo
 // kernels).  If recording fails the problem falls back to eager launches.
 int coarse_part(iss_problem* p, int l, int form, int prec, hipStream_t s, bool top) {
     Level& Lc = p->lv[l];
-    if (!top || !p->use_graphs || l == p->coarse)
+    // (the FP16 graph holds the scaled system: FP16 cycles outside the
+    // preconditioner run eagerly)
+    if (!top || !p->use_graphs || l == p->coarse || (prec == PREC_F16 && !p->f16_scaled))
         return vcycle(p, l, form, prec, Lc.w_x[prec], Lc.w_b[prec], true, s);
     VGraph& G = p->vgraph[form][prec];
     if (!G.exec) {
@@ -916,26 +939,28 @@ int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bo
     if ((rc = ensure_work(p, l, prec)) || (rc = ensure_work(p, l - 1, prec))) return rc;
     Level& L = p->lv[l];
     Level& Lc = p->lv[l - 1];
+    const LevelView& V = view(p, l, prec);
+    const LevelView& Vc = view(p, l - 1, prec);
     const int nf = p->dim + 1;
     void *xs, *bs, *ws;
     split_buffers(p, l, prec, &xs, &bs, &ws);
-    ISS_HIP(k_split(L.v, prec, nf, b, bs, SPLIT_PACK, s));
-    if (x_zero) ISS_HIP(k_fill(prec, xs, (int64_t)nf * L.v.Ns, 0.0, s));
-    else ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
+    ISS_HIP(k_split(V, prec, nf, b, bs, SPLIT_PACK, s));
+    if (x_zero) ISS_HIP(k_fill(prec, xs, (int64_t)nf * V.Ns, 0.0, s));
+    else ISS_HIP(k_split(V, prec, nf, x, xs, SPLIT_PACK, s));
     const int extra = p->opt.nu_inc * (p->levels - l);      // V_var: more steps on coarser levels
     const int nu1 = p->opt.nu1 + extra, nu2 = p->opt.nu2 + extra;
     for (int i = 0; i < nu1; ++i)
-        ISS_HIP(k_smooth_step(L.v, lform, prec, p->opt.omega, xs, bs, ws, i == 0, s));
-    ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
-    ISS_HIP(k_apply(L.v, lform, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
-    ISS_HIP(k_restrict(L.v, Lc.v, prec, L.w_r[prec], Lc.w_b[prec], s));
+        ISS_HIP(k_smooth_step(V, lform, prec, p->opt.omega, xs, bs, ws, i == 0, s));
+    ISS_HIP(k_split(V, prec, nf, xs, x, SPLIT_UNPACK, s));
+    ISS_HIP(k_apply(V, lform, BLOCK_FULL, MODE_RESID, prec, x, b, L.w_r[prec], s));
+    ISS_HIP(k_restrict(V, Vc, prec, L.w_r[prec], Lc.w_b[prec], s));
     if ((rc = coarse_part(p, l - 1, form, prec, s, l == p->levels))) return rc;
-    ISS_HIP(k_prolong_add(L.v, Lc.v, prec, Lc.w_x[prec], x, s));
+    ISS_HIP(k_prolong_add(V, Vc, prec, Lc.w_x[prec], x, s));
     if (nu2 > 0) {
-        ISS_HIP(k_split(L.v, prec, nf, x, xs, SPLIT_PACK, s));
+        ISS_HIP(k_split(V, prec, nf, x, xs, SPLIT_PACK, s));
         for (int i = 0; i < nu2; ++i)
-            ISS_HIP(k_smooth_step(L.v, lform, prec, p->opt.omega, xs, bs, ws, i == 0, s));
-        ISS_HIP(k_split(L.v, prec, nf, xs, x, SPLIT_UNPACK, s));
+            ISS_HIP(k_smooth_step(V, lform, prec, p->opt.omega, xs, bs, ws, i == 0, s));
+        ISS_HIP(k_split(V, prec, nf, xs, x, SPLIT_UNPACK, s));
     }
     return ISS_OK;
 }
@@ -964,6 +989,22 @@ int precondition(iss_problem* p, int form, int prec, const double* v, double* z,
     if (prec == PREC_F64) {
         for (int c = 0; c < p->opt.cycles; ++c)
             if ((rc = vcycle(p, l, form, PREC_F64, z, v, c == 0, s))) return rc;
+    } else if (prec == PREC_F16) {
+        // FP16 storage: FP16 holds 5 exponent bits, so the cycle runs on the
+        // symmetrically scaled system (S K S) x~ = gamma S v with S the
+        // per-field scales of the unit diagonal and gamma the inverse RMS of
+        // S v (both on the device), and z = S x~ / gamma.  The cycles are
+        // linear, so this is the same preconditioner up to rounding.
+        const int nf = p->dim + 1;
+        ISS_HIP(k_field_sumsq(PREC_F64, v, L.v.N, nf, p->d_partial, p->d_red, s));
+        ISS_HIP(k_f16_multipliers(p->d_red, nf, n, p->sig_u, p->sig_p, p->opt.f16_rms, p->d_f16mul, s));
+        ISS_HIP(k_scale_convert(prec, 0, v, L.w_b[prec], L.v.N, nf, p->d_f16mul, s));
+        p->f16_scaled = true;
+        for (int c = 0; c < p->opt.cycles && rc == ISS_OK; ++c)
+            rc = vcycle(p, l, form, prec, L.w_x[prec], L.w_b[prec], c == 0, s);
+        p->f16_scaled = false;
+        if (rc) return rc;
+        ISS_HIP(k_scale_convert(prec, 1, L.w_x[prec], z, L.v.N, nf, p->d_f16mul + nf, s));
     } else {
         // FP32 arithmetic, vectors stored in FP32 or BF16 (same exponent
         // range as FP64 needs here, so no scaling)
@@ -1218,6 +1259,7 @@ int iss_default_options(iss_options* o) {
     o->merge_max_n = 64;
     o->spec_wide_min = 65536;
     o->cycles = 1;
+    o->f16_rms = 1.0 / 1024.0;
     return ISS_OK;
 }
 
@@ -1288,6 +1330,7 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
     p->inc.assign(inclusions, inclusions + ninclusions);
     p->mu.assign(mu, mu + nphase);
     p->mu.resize(256, 1.0);
+    p->nphase = nphase;
     if (opt) p->opt = *opt;
     else iss_default_options(&p->opt);
     if (elem_phase) {
@@ -1311,7 +1354,8 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
         (p->opt.outer != ISS_OUTER_RICHARDSON && p->opt.outer != ISS_OUTER_FGMRES) ||
         (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
         p->opt.coarse_form < -1 || p->opt.coarse_form > 2 || p->opt.mid_form < -1 || p->opt.mid_form > 2 ||
-        p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0 || p->opt.cycles < 1 || p->opt.cycles > 16) {
+        p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0 || p->opt.cycles < 1 || p->opt.cycles > 16 ||
+        !(p->opt.f16_rms > 0) || !(p->opt.f16_rms < 65504.0)) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }
@@ -1336,6 +1380,7 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
         if ((rc = dev_alloc(p, (void**)&p->d_partial, 1024 * 64 * sizeof(double)))) break;
         if ((rc = dev_alloc(p, (void**)&p->d_red, 64 * sizeof(double)))) break;
         if ((rc = dev_alloc(p, (void**)&p->d_flag, 256))) break;
+        if ((rc = dev_alloc(p, (void**)&p->d_f16mul, 8 * sizeof(double)))) break;
         if (hipHostMalloc((void**)&p->h_pinned, 8192 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             rc = fail(ISS_E_NOMEM, "pinned host allocation failed");
             break;
@@ -1363,6 +1408,26 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
             rc = (dim == 3) ? setup_level<3>(p, l) : setup_level<2>(p, l);
         }
         if (rc) break;
+        // Scales of the FP16 V-cycle: S = diag(sig_u, sig_p) makes the
+        // diagonal of the finest isoviscous rows one for the viscosity
+        // sqrt(mu_min mu_max) (the geometric middle of the phases).
+        {
+            double mlo = 1e300, mhi = 0;
+            for (int i = 0; i < nphase; ++i) { mlo = std::min(mlo, mu[i]); mhi = std::max(mhi, mu[i]); }
+            const double mref = std::sqrt(mlo * mhi);
+            const LevelView& F = p->lv[levels].v;
+            const double svis0 = dim == 3 ? p->t3.Svis[0][0][0][0] : p->t2.Svis[0][0][0][0];
+            const double sc0 = dim == 3 ? p->t3.Sc[0] : p->t2.Sc[0];
+            p->sig_u = 1.0 / std::sqrt(mref * F.sA * svis0);
+            p->sig_p = 1.0 / std::sqrt(F.sC / mref * sc0);
+            for (int l = coarse_level; l <= levels; ++l) {
+                LevelView& W = p->lv[l].v16;
+                W = p->lv[l].v;
+                W.sA *= p->sig_u * p->sig_u;
+                W.sB *= p->sig_u * p->sig_p;
+                W.sC *= p->sig_p * p->sig_p;
+            }
+        }
         // keep element phases only where the coarse matrix needs them
         for (int l = coarse_level + 1; l <= levels; ++l) std::vector<uint8_t>().swap(p->lv[l].elem_phase);
     } while (0);
@@ -1664,7 +1729,7 @@ int iss_bind_workspace(iss_problem* p, void* dev_ptr, size_t bytes) {
     if (((uintptr_t)dev_ptr & (WS_ALIGN - 1)) != 0) return fail(ISS_E_INVAL, "workspace must be 256-byte aligned");
     bool used = p->d_V || p->d_rate || p->ws_base;
     for (const auto& L : p->lv)
-        for (int q = 0; q < 3; ++q) used = used || L.w_x[q] || L.w_s[q];
+        for (int q = 0; q < NPREC; ++q) used = used || L.w_x[q] || L.w_s[q];
     if (used) return fail(ISS_E_INVAL, "bind the workspace before the first call that needs work buffers");
     p->ws_base = (char*)dev_ptr;
     p->ws_size = bytes;

@@ -17,7 +17,7 @@ constexpr uint8_t OUTSIDE = 255;   // incident-element phase: outside the domain
 enum { FORM_GRADIENT = 0, FORM_STRAIN = 1, FORM_INTERFACE = 2 };
 enum { BLOCK_VEL = 0, BLOCK_FULL = 1 };
 enum { MODE_APPLY = 0, MODE_RESID = 1 };
-enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };   // storage; BF16 is computed in FP32
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_F16 = 3, NPREC = 4 };   // storage; BF16, FP16 computed in FP32
 inline int prec_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
 
 // Per-level data as seen by the kernels (all pointers are device pointers).
@@ -104,10 +104,27 @@ hipError_t k_multiaxpy(double* y, const double* X, int64_t ldx, int k, const dou
 hipError_t k_scale(double* y, double a, const double* x, int64_t n, hipStream_t s);
 hipError_t k_axpby(double* y, double a, const double* x, double b, int64_t n,
                    hipStream_t s);
+// per-field multipliers of gathered / scattered entries (entry e of a
+// vector with fields of N entries belongs to field e / N); on = 0: none
+struct FieldMul {
+    double m[4];
+    int64_t N;
+    int on;
+};
 hipError_t k_gather(int prec, const void* x, const int32_t* idx, int64_t m, double* out,
-                    hipStream_t s);
+                    hipStream_t s, FieldMul fm = FieldMul{});
 hipError_t k_scatter(int prec, const double* in, const int32_t* idx, int64_t m, void* x,
-                     hipStream_t s);
+                     hipStream_t s, FieldMul fm = FieldMul{});
+// out = in * mul[field] for nf fields of N entries between FP64 and the
+// storage precision `prec` (dir 0: FP64 in, prec out; dir 1: prec in, FP64
+// out); mul on the device
+hipError_t k_scale_convert(int prec, int dir, const void* in, void* out, int64_t N, int nf,
+                           const double* mul, hipStream_t s);
+// multipliers of the scaled FP16 V-cycle from the field sums of squares of
+// its FP64 input (device): gamma = target / RMS of (S v); in_mul[f] =
+// gamma sig_f, out_mul[f] = sig_f / gamma (mul = [in_mul | out_mul])
+hipError_t k_f16_multipliers(const double* sumsq, int nf, int64_t n, double sig_u, double sig_p, double target,
+                             double* mul, hipStream_t s);
 hipError_t k_dense_matvec(const double* A, int64_t m, const double* x, double* y,
                           hipStream_t s);
 hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* buoyant_flag, double rho,

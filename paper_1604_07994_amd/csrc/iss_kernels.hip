@@ -37,6 +37,7 @@ template <> struct ETab<2, float> { __device__ static const ElemTables<2, float>
 // Arithmetic type of a storage type: BF16-stored vectors are computed in FP32.
 template <typename T> struct Acc { using type = T; };
 template <> struct Acc<__bf16> { using type = float; };
+template <> struct Acc<_Float16> { using type = float; };
 
 template <typename T> struct Prec;
 template <> struct Prec<double> {
@@ -1749,17 +1750,49 @@ __global__ __launch_bounds__(256) void k_convert_t(const Ti* __restrict__ in, To
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_t(const T* __restrict__ x, const int32_t* __restrict__ idx,
-                                                  int64_t m, double* __restrict__ out) {
+                                                  int64_t m, double* __restrict__ out, FieldMul fm) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < m) out[e] = (double)(typename Acc<T>::type)x[idx[e]];
+    if (e >= m) return;
+    const int64_t i = idx[e];
+    const double v = (double)(typename Acc<T>::type)x[i];
+    out[e] = fm.on ? v * fm.m[i / fm.N] : v;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter_t(const double* __restrict__ in,
                                                    const int32_t* __restrict__ idx, int64_t m,
-                                                   T* __restrict__ x) {
+                                                   T* __restrict__ x, FieldMul fm) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < m) x[idx[e]] = (T)(typename Acc<T>::type)in[e];
+    if (e >= m) return;
+    const int64_t i = idx[e];
+    x[i] = (T)(typename Acc<T>::type)(fm.on ? in[e] * fm.m[i / fm.N] : in[e]);
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_scale_convert_t(const Ti* __restrict__ in, To* __restrict__ out,
+                                                         int64_t N, const double* __restrict__ mul) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= N) return;
+    const int f = blockIdx.y;
+    const double v = (double)(typename Acc<Ti>::type)in[(int64_t)f * N + e] * mul[f];
+    out[(int64_t)f * N + e] = (To)(typename Acc<To>::type)v;
+}
+
+__global__ void k_f16_mul_t(const double* __restrict__ sumsq, int nf, int64_t n, double sig_u, double sig_p,
+                            double target, double* __restrict__ mul) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double t = 0;
+    for (int f = 0; f < nf; ++f) {
+        const double sg = f + 1 < nf ? sig_u : sig_p;
+        t += sg * sg * sumsq[f];
+    }
+    const double rms = sqrt(t / (double)n);
+    const double g = (rms > 0 && isfinite(rms)) ? target / rms : 1.0;
+    for (int f = 0; f < nf; ++f) {
+        const double sg = f + 1 < nf ? sig_u : sig_p;
+        mul[f] = g * sg;
+        mul[nf + f] = sg / g;
+    }
 }
 
 // y = A x, A dense m x m row major; one wavefront per row.
@@ -1819,6 +1852,8 @@ static inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b
         case PREC_F32: { using T = float; __VA_ARGS__; }      \
         break;                                                \
         case PREC_BF16: { using T = __bf16; __VA_ARGS__; }    \
+        break;                                                \
+        case PREC_F16: { using T = _Float16; __VA_ARGS__; }   \
         break;                                                \
         default: return hipErrorInvalidValue;                 \
     }
@@ -2175,15 +2210,37 @@ hipError_t k_axpby(double* y, double a, const double* x, double b, int64_t n, hi
     return hipGetLastError();
 }
 
-hipError_t k_gather(int prec, const void* x, const int32_t* idx, int64_t m, double* out, hipStream_t s) {
+hipError_t k_gather(int prec, const void* x, const int32_t* idx, int64_t m, double* out, hipStream_t s,
+                    FieldMul fm) {
     ISS_BY_PREC(prec,
-        hipLaunchKernelGGL((k_gather_t<T>), grid1(m), dim3(256), 0, s, (const T*)x, idx, m, out))
+        hipLaunchKernelGGL((k_gather_t<T>), grid1(m), dim3(256), 0, s, (const T*)x, idx, m, out, fm))
     return hipGetLastError();
 }
 
-hipError_t k_scatter(int prec, const double* in, const int32_t* idx, int64_t m, void* x, hipStream_t s) {
+hipError_t k_scatter(int prec, const double* in, const int32_t* idx, int64_t m, void* x, hipStream_t s,
+                     FieldMul fm) {
     ISS_BY_PREC(prec,
-        hipLaunchKernelGGL((k_scatter_t<T>), grid1(m), dim3(256), 0, s, in, idx, m, (T*)x))
+        hipLaunchKernelGGL((k_scatter_t<T>), grid1(m), dim3(256), 0, s, in, idx, m, (T*)x, fm))
+    return hipGetLastError();
+}
+
+hipError_t k_scale_convert(int prec, int dir, const void* in, void* out, int64_t N, int nf, const double* mul,
+                           hipStream_t s) {
+    if (N <= 0 || nf <= 0) return hipSuccess;
+    const dim3 g((unsigned)((N + 255) / 256), (unsigned)nf);
+    if (dir == 0) {
+        ISS_BY_PREC(prec,
+            hipLaunchKernelGGL((k_scale_convert_t<double, T>), g, dim3(256), 0, s, (const double*)in, (T*)out, N, mul))
+    } else {
+        ISS_BY_PREC(prec,
+            hipLaunchKernelGGL((k_scale_convert_t<T, double>), g, dim3(256), 0, s, (const T*)in, (double*)out, N, mul))
+    }
+    return hipGetLastError();
+}
+
+hipError_t k_f16_multipliers(const double* sumsq, int nf, int64_t n, double sig_u, double sig_p, double target,
+                             double* mul, hipStream_t s) {
+    hipLaunchKernelGGL(k_f16_mul_t, dim3(1), dim3(64), 0, s, sumsq, nf, n, sig_u, sig_p, target, mul);
     return hipGetLastError();
 }
 

@@ -93,7 +93,8 @@ def test_problem_create_rejects_split_field_beyond_4gib():
 @pytest.mark.parametrize("field,value", [("nu1", -1), ("nu_inc", -2), ("restart", 0), ("outer", 5),
                                          ("coarse_mu", 7), ("coarse_form", 3), ("stab_beta", 0.0),
                                          ("mid_form", -2), ("mid_form", 3), ("merge_max_n", -1),
-                                         ("spec_wide_min", -1), ("cycles", 0), ("cycles", 17)])
+                                         ("spec_wide_min", -1), ("cycles", 0), ("cycles", 17), ("f16_rms", 0.0),
+                                         ("f16_rms", 1e5)])
 def test_problem_create_rejects_bad_options(field, value):
     from paper_1604_07994_amd import binding
     L = binding.lib()

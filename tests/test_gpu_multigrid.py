@@ -128,12 +128,12 @@ def test_richardson_solve_2d_matches_oracle():
         P.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
 def test_fgmres_solve_3d_high_contrast(prec):
     """Contrast 1e3 (sphere): FGMRES with one V-cycle per iteration reaches
-    1e-8 on the FP64 residual with the V-cycle in FP64, FP32 or FP32 with
-    BF16-stored vectors; the FP64
-    history matches the oracle FGMRES to 3 digits."""
+    1e-8 on the FP64 residual with the V-cycle in FP64, FP32, FP32 with
+    BF16-stored vectors or FP32 with FP16-stored vectors (on the scaled
+    system); the FP64 history matches the oracle FGMRES to 3 digits."""
     import torch
     w = small_workload("sphere_3d", 4)
     b = iss_inputs.random_rhs(3, w["n"], seed=4)

@@ -98,6 +98,25 @@ def test_apply_bf16_storage(case, form):
     assert np.all(err <= bound), (form, float(np.max(err - bound)))
 
 
+@pytest.mark.parametrize("form", ["strain", "interface"])
+def test_apply_fp16_storage(case, form):
+    """FP16-stored vectors, FP32 arithmetic: the input is the FP16 rounding
+    of x, the output is rounded to FP16 once (unit roundoff 2^-11; entries
+    below 2^-14 are subnormal with spacing 2^-24)."""
+    import torch
+    w, P, D = case
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=15)
+    xh = to_dev(x, torch.float16)
+    K = D.stokes(form)
+    xr = to_host(xh)
+    ref = K @ xr
+    y = torch.empty(x.size, dtype=torch.float16, device="cuda")
+    P.apply(form, xh, y)
+    err = np.abs(to_host(y) - ref)
+    bound = 2.0 ** -11 * np.abs(ref) + 4e-6 * np.max(abs_scale(K, xr)) + 2.0 ** -24
+    assert np.all(err <= bound), (form, float(np.max(err - bound)))
+
+
 @pytest.mark.parametrize("form", ["gradient", "strain", "interface"])
 def test_residual_and_norms(case, form):
     import torch
