@@ -141,6 +141,13 @@ typedef struct {
                            * 2^-10: the cycle's corrections exceed its input
                            * by up to the inverse of the smallest eigenvalue,
                            * and FP16 ends at 65504). */
+    int coarse_rhs_mod;   /* nonzero: when the coarsest level takes another
+                           * form than the level above it, its right-hand
+                           * side r_1 becomes r_1 + B^T M^-1 r_2, M the
+                           * lumped (1/mu)-weighted pressure mass (Sec. 5,
+                           * coarse grid solver; the paper's minus sign
+                           * belongs to its opposite sign of B), folded
+                           * into the coarse inverse at setup.  Default 0. */
 } iss_options;
 
 typedef struct {

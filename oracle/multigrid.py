@@ -226,7 +226,7 @@ class Hierarchy:
 
     def __init__(self, dim, m, fine_level, coarse_level, inclusions, mu_table, form,
                  nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None, nu_inc=0,
-                 mid_form=None, table=None):
+                 mid_form=None, table=None, coarse_rhs_mod=False):
         """coarse_mu: 'centroid' rediscretises every level with the centroid
         rule; 'average' uses averaged_coarse_viscosity below the finest
         level (``table``: its table-size model, None = exact averages).
@@ -235,7 +235,11 @@ class Hierarchy:
         coarsest level (Sec. 5 swaps to the strain form on the coarse grid;
         default: the form of the levels above).  nu_inc: variable V-cycle
         (V_var of Sec. 5), nu_inc more pre- and post-smoothing steps per
-        level below the finest."""
+        level below the finest.  coarse_rhs_mod: when the coarsest level's
+        form differs from the one above it, its momentum right-hand side
+        r_1 is replaced by r_1 + B^T M^-1 r_2 with M the lumped
+        (1/mu)-weighted pressure mass (Sec. 5, coarse grid solver; the
+        paper writes r_1 - B^T M^-1 r_2 for its opposite sign of B)."""
         self.dim = dim
         self.levels = {}
         self.P = {}
@@ -257,6 +261,8 @@ class Hierarchy:
         self.fine, self.coarse = fine_level, coarse_level
         self.coarse_solver = CoarseSolver(self.levels[coarse_level])
         self.nu1, self.nu2, self.omega, self.nu_inc = nu1, nu2, omega, nu_inc
+        self.coarse_rhs_mod = (coarse_rhs_mod and fine_level > coarse_level and
+                               self.levels[coarse_level].form != self.levels[coarse_level + 1].form)
 
     def prolong(self, l, xc):
         P, dim = self.P[l], self.dim
@@ -272,6 +278,10 @@ class Hierarchy:
     def vcycle(self, l, x, b):
         lv = self.levels[l]
         if l == self.coarse:
+            if self.coarse_rhs_mod:
+                N, d = lv.N, self.dim
+                b = b.copy()
+                b[:d * N] += lv.BT @ (b[d * N:] / lv.weights)
             return self.coarse_solver.solve(b)
         extra = self.nu_inc * (self.fine - l)
         x = smooth(lv, x, b, self.nu1 + extra, self.omega)

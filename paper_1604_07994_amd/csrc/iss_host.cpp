@@ -211,6 +211,7 @@ struct Coarse {
     std::vector<int32_t> free_idx;
     int32_t* d_free = nullptr;
     double* d_Kinv[3] = {nullptr, nullptr, nullptr};
+    double* d_Kinv_mod[3] = {nullptr, nullptr, nullptr};   // K^-1 T: right-hand side modified
     double* d_bc = nullptr;
     double* d_xc = nullptr;
 };
@@ -816,16 +817,47 @@ int dense_inverse(std::vector<double>& A, int64_t M) {
     return ISS_OK;
 }
 
-int ensure_coarse(iss_problem* p, int form) {
+// Inverse of the bordered coarse matrix of `form`; with mod, the inverse
+// times T = [[I, B^T M^-1], [0, I]], M the lumped (1/mu)-weighted pressure
+// mass (the weights of the pressure constraint): the coarse right-hand side
+// r_1 becomes r_1 + B^T M^-1 r_2 (Sec. 5, coarse grid solver; the sign
+// follows b(v, q) = -(div v, q)), which makes the strain-form coarse system
+// approximate the a_tr system of the finer levels where div u != 0.
+int ensure_coarse(iss_problem* p, int form, bool mod = false) {
     Coarse& cs = p->cs;
-    if (cs.d_Kinv[form]) return ISS_OK;
+    if (mod ? cs.d_Kinv_mod[form] : cs.d_Kinv[form]) return ISS_OK;
     std::vector<double> Kd;
     int64_t M;
     std::vector<int32_t> fidx;
     if (p->dim == 3) coarse_matrix<3>(p, form, Kd, M, fidx);
     else coarse_matrix<2>(p, form, Kd, M, fidx);
+    // per pressure column c: the entries of B^T M^-1 in the velocity rows
+    std::vector<std::vector<std::pair<int64_t, double>>> E;
+    if (mod) {
+        const int64_t m = M - 1;
+        const int64_t NpStart = (int64_t)p->dim * p->lv[p->coarse].v.N;
+        E.resize(M);
+        for (int64_t c = 0; c < m; ++c) {
+            if (fidx[c] < NpStart) continue;                     // pressure columns only
+            const double wj = Kd[(size_t)m * M + c];              // border row: the weight
+            for (int64_t r = 0; r < m; ++r)
+                if (fidx[r] < NpStart && Kd[(size_t)r * M + c] != 0.0)
+                    E[c].emplace_back(r, Kd[(size_t)r * M + c] / wj);
+        }
+    }
     int rc;
     if ((rc = dense_inverse(Kd, M))) return rc;
+    if (mod) {
+        // (K^-1 T)[:, c] = K^-1[:, c] + sum_r K^-1[:, r] E[r][c] (row-major)
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < M; ++i) {
+            double* row = &Kd[(size_t)i * M];
+            std::vector<double> add(M, 0.0);
+            for (int64_t c = 0; c < M; ++c)
+                for (const auto& e : E[c]) add[c] += row[e.first] * e.second;
+            for (int64_t c = 0; c < M; ++c) row[c] += add[c];
+        }
+    }
     if (!cs.d_free) {
         cs.M = M;
         cs.free_idx = fidx;
@@ -834,8 +866,16 @@ int ensure_coarse(iss_problem* p, int form) {
         if ((rc = dev_alloc(p, (void**)&cs.d_xc, M * sizeof(double)))) return rc;
         ISS_HIP(hipMemset(cs.d_bc, 0, M * sizeof(double)));
     }
-    if ((rc = dev_upload(p, &cs.d_Kinv[form], Kd.data(), Kd.size()))) return rc;
+    if ((rc = dev_upload(p, mod ? &cs.d_Kinv_mod[form] : &cs.d_Kinv[form], Kd.data(), Kd.size()))) return rc;
     return ISS_OK;
+}
+
+// the coarse right-hand side is modified when the coarsest level swaps to
+// another form than the level above it uses (option coarse_rhs_mod)
+int level_form(const iss_problem* p, int l, int form);
+bool coarse_mod(const iss_problem* p, int form) {
+    return p->opt.coarse_rhs_mod && p->levels > p->coarse &&
+           level_form(p, p->coarse, form) != level_form(p, p->coarse + 1, form);
 }
 
 // ----------------------------------------------------------------------------
@@ -864,9 +904,9 @@ int level_form(const iss_problem* p, int l, int form) {
     return mid;
 }
 
-int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hipStream_t s) {
+int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hipStream_t s, bool mod = false) {
     int rc;
-    if ((rc = ensure_coarse(p, form))) return rc;
+    if ((rc = ensure_coarse(p, form, mod))) return rc;
     Coarse& cs = p->cs;
     const Level& L = p->lv[p->coarse];
     const int64_t m = cs.M - 1;
@@ -878,7 +918,7 @@ int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hip
         fm.on = 1;
     }
     ISS_HIP(k_gather(prec, b, cs.d_free, m, cs.d_bc, s, fm));
-    ISS_HIP(k_dense_matvec(cs.d_Kinv[form], cs.M, cs.d_bc, cs.d_xc, s));
+    ISS_HIP(k_dense_matvec(mod ? cs.d_Kinv_mod[form] : cs.d_Kinv[form], cs.M, cs.d_bc, cs.d_xc, s));
     ISS_HIP(k_fill(prec, x, (int64_t)(p->dim + 1) * L.v.N, 0.0, s));
     ISS_HIP(k_scatter(prec, cs.d_xc, cs.d_free, m, x, s, fm));
     return ISS_OK;
@@ -933,7 +973,7 @@ int coarse_part(iss_problem* p, int l, int form, int prec, hipStream_t s, bool t
 }
 
 int vcycle(iss_problem* p, int l, int form, int prec, void* x, const void* b, bool x_zero, hipStream_t s) {
-    if (l == p->coarse) return coarse_solve(p, level_form(p, l, form), prec, b, x, s);
+    if (l == p->coarse) return coarse_solve(p, level_form(p, l, form), prec, b, x, s, coarse_mod(p, form));
     const int lform = level_form(p, l, form);
     int rc;
     if ((rc = ensure_work(p, l, prec)) || (rc = ensure_work(p, l - 1, prec))) return rc;
@@ -1068,7 +1108,7 @@ int solve(iss_problem* p, int form, int prec, double rtol, int maxit, double* x,
     const int m = std::max(1, p->opt.restart);
     int rc;
     if ((rc = ensure_krylov(p, m))) return rc;
-    if ((rc = ensure_coarse(p, level_form(p, p->coarse, form)))) return rc;
+    if ((rc = ensure_coarse(p, level_form(p, p->coarse, form), coarse_mod(p, form)))) return rc;
     double sq[4];
     if ((rc = field_norms(p, PREC_F64, b, N, D + 1, sq, s))) return rc;
     const double nb = total_norm(sq, D + 1);
@@ -1260,6 +1300,7 @@ int iss_default_options(iss_options* o) {
     o->spec_wide_min = 65536;
     o->cycles = 1;
     o->f16_rms = 1.0 / 1024.0;
+    o->coarse_rhs_mod = 0;
     return ISS_OK;
 }
 

@@ -278,6 +278,26 @@ def test_vcycle_default_configuration(name, levels, mid):
     P.close()
 
 
+@pytest.mark.parametrize("name,levels", [("sphere_3d", 4), ("sinker_3d", 4)])
+def test_vcycle_coarse_rhs_modification(name, levels):
+    """The paper's configuration with its coarse right-hand-side
+    modification: interface form on every level but the coarsest, strain
+    form there with r_1 + B^T M^-1 r_2 (Sec. 5), against the oracle."""
+    w = small_workload(name, levels)
+    P = gpu_problem(w, coarse_mu="average", coarse_form="strain", omega=0.6, nu1=3, nu2=3, coarse_rhs_mod=True)
+    H = mg.Hierarchy(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"],
+                     "interface", nu1=3, nu2=3, omega=0.6, coarse_mu="average", coarse_form="strain",
+                     coarse_rhs_mod=True)
+    assert H.coarse_rhs_mod
+    x = iss_inputs.random_vector(w["dim"], w["n"], seed=37)
+    b = iss_inputs.random_rhs(w["dim"], w["n"], seed=38)
+    xg = to_dev(x)
+    P.vcycle("interface", xg, to_dev(b))
+    ref = H.vcycle(w["levels"], x, b)
+    assert _rel(to_host(xg), ref) < 1e-10
+    P.close()
+
+
 def test_vcycle_variable_smoothing():
     """V_var: two more smoothing steps per coarser level, against the
     oracle hierarchy with the same schedule."""
