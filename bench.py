@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--quick", action="store_true", help="solves only, no apply/smoother timing")
+    ap.add_argument("--no-columns", action="store_true",
+                    help="skip the viscosity-columns timing problem of the paper (257^3, free-slip)")
     return ap.parse_args()
 
 
@@ -142,6 +144,55 @@ def measured_traffic(kernel, form):
     if not entry or rec.get("iss_kernels_sha256") != digest:
         return None
     return entry["bytes_per_launch"]
+
+
+# Sec. 5, Table timeANDconv: time of one V_var(3,3) cycle and asymptotic
+# rate per form on the viscosity-columns problem, level 6 (257^3), on a
+# 32-core Xeon server: for comparison only (another machine)
+PAPER_COLUMNS_L6 = {"strain": {"cycle_s": 3.02, "rate": 0.280},
+                    "interface": {"cycle_s": 2.45, "rate": 0.242},
+                    "gradient": {"cycle_s": 2.64, "rate": 0.240}}
+
+
+def columns_report(rate_iters, reps=5):
+    """The paper's timing problem: viscosity columns (mu 1 / 10, free-slip)
+    at 257^3 with its multigrid settings (Uzawa V(3,3) with 2 more steps per
+    coarser level, omega 0.3, strain form on the coarsest level, averaged
+    coarse viscosity): per form the time of one V-cycle (HIP events), the
+    asymptotic rate and the stationary iterations to 1e-8 from zero."""
+    import numpy as np
+    import torch
+    import iss_inputs
+    from paper_1604_07994_amd import Problem
+    w = iss_inputs.workload("columns_3d")
+    P = Problem.from_workload(w, outer="richardson", omega=0.3, nu1=3, nu2=3, nu_inc=2, coarse_mu="average",
+                              coarse_form="strain")
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(np.ascontiguousarray(iss_inputs.column_force(3, w["n"]).ravel())).to(dev)
+    b = torch.empty(P.vector_size(), dtype=torch.float64, device=dev)
+    P.rhs_nodal_force(f, b)
+    del f
+    x0 = torch.from_numpy(iss_inputs.random_vector(3, w["n"], seed=8, bc="freeslip")).to(dev)
+    out = {}
+    for form in ("interface", "strain", "gradient"):
+        x = torch.zeros_like(b)
+        P.vcycle(form, x, b)
+        ms = event_time(lambda: P.vcycle(form, x, b), reps)
+        hist = P.asymptotic_rate(form, x0.clone(), iters=rate_iters) if rate_iters > 0 else [float("nan")]
+        x.zero_()
+        info = P.solve(form, x, b, rtol=1e-8, maxit=60, raise_on_fail=False)
+        out[form] = {"cycle_ms": ms, "rate": hist[-1], "rate_iterations": rate_iters,
+                     "iterations_to_1e-8": info["iterations"], "relres": info["relres"],
+                     "solve_s": info["seconds"], "paper_xeon32": PAPER_COLUMNS_L6[form]}
+        log("columns %s: V-cycle %.2f ms, rate %.4f, %d its to %.1e in %.3f s" %
+            (form, ms, hist[-1], info["iterations"], info["relres"], info["seconds"]))
+    P.close()
+    return {"workload": "columns_3d: 257^3 vertices, mu 1 / 10 columns (0,1/4)^2 x (0,1) and (3/4,1)^2 x (0,1), "
+                        "free-slip, f = (0, 0, -cos 2 pi x cos 2 pi y sin pi z)",
+            "cycle": "Uzawa V(3,3) +2 steps per coarser level, omega 0.3, averaged coarse viscosity, strain form "
+                     "on the coarsest level (9^3), FP64",
+            "forms": out,
+            "strain_over_interface_cycle": out["strain"]["cycle_ms"] / out["interface"]["cycle_ms"]}
 
 
 def learned_report(seeds=(100000, 100004)):
@@ -354,6 +405,12 @@ def main():
                                                                    info["status"]))
         Pp.close()
 
+    columns = None
+    if not args.no_columns:
+        P.close()
+        torch.cuda.empty_cache()
+        columns = columns_report(args.rate_iters)
+
     main_form = forms[0]
     value = results[main_form]["seconds"]
     # Roofline of the dominant kernel, the bulk velocity Gauss-Seidel colour
@@ -412,6 +469,7 @@ def main():
         "apply": apply_gbs,
         "smooth_step_ms": smooth_ms,
         "paper_configuration": paper_cfg,
+        "viscosity_columns": columns,
         "asymptotic_rate": rates,
         "roofline": roof,
         "roofline_smoothing_step": roof_step,

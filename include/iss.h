@@ -5,14 +5,17 @@
  * for subdomain-wise isoviscous Stokes finite element discretizations"
  * (arXiv:1604.07994).  Stabilised P1-P1 Stokes on uniformly refined
  * simplicial macro meshes (Kuhn lattices), piecewise constant viscosity,
- * homogeneous Dirichlet velocity on the whole boundary.  The viscous block
+ * and on the whole boundary either homogeneous Dirichlet velocity (no-slip,
+ * the default) or free-slip, u . n = 0 with zero tangential traction
+ * (eq. boundary; option bc).  The viscous block
  * is one of
  *   ISS_GRADIENT   (mu grad u, grad v) everywhere (Sec. 1; inconsistent),
  *   ISS_STRAIN     a_sym = (2 mu sym grad u, sym grad v)   (eq. standard),
  *   ISS_INTERFACE  a_tr = a_sym - (mu div u, div v)        (eq. newbil),
  *                  applied as in eq. equivalence-stencil: the decoupled
  *                  Laplacian stencil per component on isoviscous rows and
- *                  the full a_tr rows only at interface vertices.
+ *                  the full a_tr rows only at interface vertices and, for
+ *                  free-slip, at boundary vertices (Gamma_F, Sec. 2.2).
  * The saddle-point matrix is K = [[A, B^T], [B, -C]] (Sec. 5) with the
  * weak divergence b(v, q) = -(div v, q) (eq. weaks) and the pressure
  * stabilisation c(p, q) = sum_T beta h^2 / mu_T (grad p, grad q)_T.
@@ -21,8 +24,10 @@
  * N = (n+1)^d lattice vertices, vertex v = i + (n+1) (j + (n+1) k), x
  * fastest, coordinates (i, j, k) / n on the unit cube (square).  A vector
  * is d+1 contiguous fields [u_1 | ... | u_d | p], each of length N, so
- * (d+1) N elements in total.  Velocity entries of boundary vertices are
- * Dirichlet values: inputs must hold 0 there and outputs hold 0 there.
+ * (d+1) N elements in total.  Fixed velocity entries -- every component of
+ * a boundary vertex for no-slip; for free-slip component k of a vertex on
+ * a face x_k = 0 or 1 -- are zero Dirichlet values: inputs must hold 0
+ * there and outputs hold 0 there.
  * Pressure lives on every vertex.  Element type: double for ISS_FP64,
  * float for ISS_FP32, bfloat16 (1-8-7 bits, round to nearest even) for
  * ISS_FP32_BF16STORE and IEEE half (1-5-10 bits) for ISS_FP32_FP16STORE,
@@ -73,18 +78,22 @@ enum iss_form { ISS_GRADIENT = 0, ISS_STRAIN = 1, ISS_INTERFACE = 2 };
 enum iss_block { ISS_VELOCITY_ONLY = 0, ISS_FULL_STOKES = 1 };
 enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1, ISS_FP32_BF16STORE = 2, ISS_FP32_FP16STORE = 3 };
 enum iss_outer { ISS_OUTER_RICHARDSON = 0, ISS_OUTER_FGMRES = 1 };
-enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1 };
+enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1, ISS_BOX = 2 };
+enum iss_bc { ISS_BC_NOSLIP = 0, ISS_BC_FREESLIP = 1 };
 enum iss_coarse_mu { ISS_COARSE_MU_CENTROID = 0, ISS_COARSE_MU_AVERAGE = 1 };
 
-/* A viscosity inclusion.  Sphere: a = (cx, cy, cz, r), region |x-c| < r
- * (cz ignored in 2D).  Half-space: a = (axis, threshold, -, -), region
- * x[axis] < threshold.  An element takes the phase of the first inclusion
+/* A viscosity inclusion.  Sphere: a = (cx, cy, cz, r, -, -), region
+ * |x-c| < r (cz ignored in 2D).  Half-space: a = (axis, threshold, -, ..),
+ * region x[axis] < threshold.  Box: a = (x0, x1, y0, y1, z0, z1), region
+ * x0 < x < x1, y0 < y < y1, z0 < z < z1 (z ignored in 2D; the viscosity
+ * columns of Sec. 4 are two such boxes).  An element takes the phase of
+ * the first inclusion
  * (array order) whose region contains its centroid, else phase 0 (the
  * unresolved-interface setting of the remark closing Sec. 2.2). */
 typedef struct {
     int kind;
     int phase;            /* 1..nphase-1 */
-    double a[4];
+    double a[6];
 } iss_inclusion;
 
 typedef struct {
@@ -148,6 +157,15 @@ typedef struct {
                            * coarse grid solver; the paper's minus sign
                            * belongs to its opposite sign of B), folded
                            * into the coarse inverse at setup.  Default 0. */
+    int bc;               /* boundary condition on the whole boundary of
+                           * every level (eq. boundary): ISS_BC_NOSLIP
+                           * (default) or ISS_BC_FREESLIP.  Free-slip fixes
+                           * the normal velocity component on each face;
+                           * the tangential components of boundary vertices
+                           * are unknowns whose rows take the full element
+                           * rows of the form (a_tr for ISS_INTERFACE, as
+                           * Sec. 2.2 requires on Gamma_F).  Not with the
+                           * learned band correction (iss_net_create). */
 } iss_options;
 
 typedef struct {
@@ -227,6 +245,17 @@ int iss_vertex_class(const iss_problem* p, int level, uint8_t* cls,
  * the finest level carries the problem's phases (ISS_E_INVAL otherwise). */
 int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
                      double rho, double* b, iss_stream_t stream);
+
+/* Load of a body force given by its nodal values: b_k = M f_k for each
+ * velocity component k, M the P1 mass matrix of `level` (the right-hand
+ * side (f, v) of the weak form of Sec. 1 for the P1 interpolant of f),
+ * fixed velocity entries and the pressure field zero.  f: device FP64,
+ * d fields of N nodal values [f_1 | .. | f_d] (the caller evaluates f at
+ * the vertices); b: device FP64 vector of (d+1) N entries, overwritten.
+ * Sec. 4 forces the viscosity layers and columns with
+ * f = (0, 0, -cos(2 pi x) cos(2 pi y) sin(pi z)). */
+int iss_rhs_nodal_force(iss_problem* p, int level, const double* f, double* b,
+                        iss_stream_t stream);
 
 /* y = K x (block ISS_FULL_STOKES) or y = (A x_u, 0) (ISS_VELOCITY_ONLY) at
  * `level` with the viscous form `form`: the saddle-point operator of the

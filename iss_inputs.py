@@ -21,7 +21,7 @@ times its own viscosity-columns problem, Sec. 4-5):
 """
 import numpy as np
 
-HALFSPACE, SPHERE = 'halfspace', 'sphere'
+HALFSPACE, SPHERE, BOX = 'halfspace', 'sphere', 'box'
 
 
 def _sphere(c, r, phase=1):
@@ -49,6 +49,14 @@ def workload(name, seed=0, levels=None):
         w = dict(dim=3, macro=2, levels=7, coarse=2,
                  inclusions=[_sphere(c, r) for c, r in zip(centres, radii)],
                  mu=[1.0, 1.0e4], buoyant=[1])
+    elif name == 'columns_3d':
+        # viscosity columns: the unit cube as 4^3 macro cubes, mu 10 in the
+        # columns (0, 1/4)^2 x (0, 1) and (3/4, 1)^2 x (0, 1), mu 1 elsewhere,
+        # free-slip on the whole boundary, forced by column_force below
+        w = dict(dim=3, macro=4, levels=6, coarse=1,
+                 inclusions=[{'kind': BOX, 'lo': (0.0, 0.0, 0.0), 'hi': (0.25, 0.25, 1.0), 'phase': 1},
+                             {'kind': BOX, 'lo': (0.75, 0.75, 0.0), 'hi': (1.0, 1.0, 1.0), 'phase': 1}],
+                 mu=[1.0, 10.0], buoyant=[], bc='freeslip', force='columns')
     elif name == 'learned_3d':
         rng = np.random.default_rng(seed)
         k = int(rng.integers(1, 17))
@@ -74,29 +82,49 @@ def interior_mask(dim, n):
     return np.all((idx > 0) & (idx < n), axis=0)
 
 
-def random_rhs(dim, n, seed):
-    """b = (f, g) with f ~ U[-1, 1] on velocity entries of interior vertices,
-    zero on boundary vertices, and g = 0.  Field-major [f_1..f_d | g]."""
+def velocity_mask(dim, n, k, bc='noslip'):
+    """1 where velocity component k is an unknown: interior vertices for
+    'noslip'; for 'freeslip' every vertex off the faces x_k = 0, 1."""
+    if bc == 'noslip':
+        return interior_mask(dim, n)
+    idx = np.indices((n + 1,) * dim).reshape(dim, -1)[::-1]
+    return (idx[k] > 0) & (idx[k] < n)
+
+
+def random_rhs(dim, n, seed, bc='noslip'):
+    """b = (f, g) with f ~ U[-1, 1] on velocity entries that are unknowns,
+    zero on fixed ones, and g = 0.  Field-major [f_1..f_d | g]."""
     rng = np.random.default_rng(seed)
     N = (n + 1) ** dim
     b = np.zeros((dim + 1) * N)
-    m = interior_mask(dim, n)
     for k in range(dim):
-        b[k * N:(k + 1) * N] = rng.uniform(-1.0, 1.0, N) * m
+        b[k * N:(k + 1) * N] = rng.uniform(-1.0, 1.0, N) * velocity_mask(dim, n, k, bc)
     return b
 
 
-def random_vector(dim, n, seed, zero_dirichlet=True):
-    """x ~ U[-1, 1] on every entry; velocity entries of boundary vertices are
-    zero when zero_dirichlet is set (the operators assume that)."""
+def random_vector(dim, n, seed, zero_dirichlet=True, bc='noslip'):
+    """x ~ U[-1, 1] on every entry; fixed velocity entries are zero when
+    zero_dirichlet is set (the operators assume that)."""
     rng = np.random.default_rng(seed)
     N = (n + 1) ** dim
     x = rng.uniform(-1.0, 1.0, (dim + 1) * N)
     if zero_dirichlet:
-        m = interior_mask(dim, n)
         for k in range(dim):
-            x[k * N:(k + 1) * N] *= m
+            x[k * N:(k + 1) * N] *= velocity_mask(dim, n, k, bc)
     return x
+
+
+def column_force(dim, n):
+    """Nodal values (d fields of N) of the body force of the viscosity
+    layers and columns, f = (0, 0, -cos(2 pi x) cos(2 pi y) sin(pi z)) in 3D
+    (2D: f = (0, -cos(2 pi x) sin(pi y)))."""
+    idx = np.indices((n + 1,) * dim).reshape(dim, -1)[::-1] / n
+    f = np.zeros((dim, idx.shape[1]))
+    if dim == 3:
+        f[2] = -np.cos(2 * np.pi * idx[0]) * np.cos(2 * np.pi * idx[1]) * np.sin(np.pi * idx[2])
+    else:
+        f[1] = -np.cos(2 * np.pi * idx[0]) * np.sin(np.pi * idx[1])
+    return f
 
 
 def sample_vertices(dim, n, count, seed):

@@ -6,9 +6,11 @@ layout [u_1 | .. | u_d | p] used by every vector of the project.
 
 The saddle-point system of Sec. 5 is K = [[A, B^T], [B, -C]] with A from one
 of the viscous forms, B the weak divergence (eq. weaks) and C the pressure
-stabilisation.  Dirichlet velocity dofs (the whole boundary) are handled by
-masking: rows and columns of fixed dofs are zero, so K acts on vectors whose
-boundary velocity entries are ignored and returns zero there.
+stabilisation.  Fixed velocity dofs (eq. boundary: every component on the
+boundary for no-slip, the normal component for free-slip; see
+mesh.fixed_velocity) are handled by masking: rows and columns of fixed dofs
+are zero, so K acts on vectors whose fixed entries are ignored and returns
+zero there.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -26,8 +28,9 @@ class Discretisation:
     only rows of vertices whose incident elements are all present are
     meaningful."""
 
-    def __init__(self, dim, n, inclusions, mu_table, elems=None, mu_e=None, imu_e=None):
+    def __init__(self, dim, n, inclusions, mu_table, elems=None, mu_e=None, imu_e=None, bc='noslip'):
         self.dim, self.n = dim, n
+        self.bc = bc
         self.N = mesh.num_vertices(dim, n)
         self.h = 1.0 / n
         self.elems = mesh.kuhn_elements(dim, n) if elems is None else elems
@@ -42,6 +45,7 @@ class Discretisation:
         self.G, self.vol = fem.simplex_geometry(X)
         self.interface = problem.interface_vertices(dim, n, self.elems, self.mu_e)
         self.boundary = mesh.boundary_mask(dim, n)
+        self.fixed = mesh.fixed_velocity(dim, n, bc)     # (dim, N)
 
     # -- dof bookkeeping ---------------------------------------------------
     @property
@@ -49,10 +53,9 @@ class Discretisation:
         return (self.dim + 1) * self.N
 
     def free_mask(self):
-        """Velocity dofs of interior vertices and every pressure dof."""
+        """Velocity dofs that are not fixed, and every pressure dof."""
         f = np.ones(self.ndof, dtype=bool)
-        for k in range(self.dim):
-            f[k * self.N:(k + 1) * self.N] = ~self.boundary
+        f[:self.dim * self.N] = ~self.fixed.ravel()
         return f
 
     def _velocity_dofs(self):
@@ -81,8 +84,11 @@ class Discretisation:
         'strain'    : a_sym, eq. standard
         'tr'        : a_tr, eq. newbil
         'interface' : the row-wise operator of eq. equivalence-stencil --
-                      rows of interface vertices from a_tr, every other row
-                      from the isoviscous Laplacian (mu grad u, grad v).
+                      rows of interface and boundary vertices from a_tr,
+                      every other row from the isoviscous Laplacian
+                      (mu grad u, grad v).  The full rows on the boundary are
+                      those Sec. 2.2 asks for on Gamma_F; on Dirichlet
+                      vertices the rows are masked anyway.
         """
         d, N = self.dim, self.N
         vd = self._velocity_dofs()
@@ -93,7 +99,7 @@ class Discretisation:
         if form == 'interface':
             A_lap = self.viscous('gradient')
             A_tr = self.viscous('tr')
-            rows_if = np.tile(self.interface, d).astype(np.float64)
+            rows_if = np.tile(self.interface | self.boundary, d).astype(np.float64)
             return sp.diags(rows_if) @ A_tr + sp.diags(1.0 - rows_if) @ A_lap
         raise ValueError(form)
 
@@ -128,13 +134,13 @@ class Discretisation:
     def velocity_operator(self, form, masked=True):
         A = self.viscous(form)
         if masked:
-            D = sp.diags(np.tile(~self.boundary, self.dim).astype(np.float64))
+            D = sp.diags((~self.fixed.ravel()).astype(np.float64))
             A = (D @ A @ D).tocsr()
         A.eliminate_zeros()
         return A
 
 
-def sampled_rows(dim, n, inclusions, mu_table, verts):
+def sampled_rows(dim, n, inclusions, mu_table, verts, bc='noslip'):
     """A Discretisation restricted to the elements incident to ``verts``.
 
     Rows of ``verts`` of any operator assembled from it equal the rows of
@@ -142,16 +148,16 @@ def sampled_rows(dim, n, inclusions, mu_table, verts):
     contain its vertex); all other rows are incomplete and must not be used.
     """
     elems = mesh.incident_elements(dim, n, verts)
-    return Discretisation(dim, n, inclusions, mu_table, elems=elems)
+    return Discretisation(dim, n, inclusions, mu_table, elems=elems, bc=bc)
 
 
-def sampled_stokes_rows(dim, n, inclusions, mu_table, verts, form, x):
+def sampled_stokes_rows(dim, n, inclusions, mu_table, verts, form, x, bc='noslip'):
     """Rows of y = K x at the vertices ``verts`` (all d+1 fields) without
     assembling K globally: the element matrices of the elements incident to
     the sample are scattered only into sample rows.  Dirichlet masking as in
     Discretisation.stokes.  Returns Y with Y[f, i] = y[f * N + verts[i]]."""
     verts = np.unique(np.asarray(verts, dtype=np.int64))
-    D = sampled_rows(dim, n, inclusions, mu_table, verts)
+    D = sampled_rows(dim, n, inclusions, mu_table, verts, bc=bc)
     N = D.N
     d = dim
     lookup = {int(v): i for i, v in enumerate(verts)}
@@ -162,8 +168,7 @@ def sampled_stokes_rows(dim, n, inclusions, mu_table, verts, form, x):
         Kl = fem.viscous_element_matrices(D.G, D.vol, D.mu_e, 'lap')
     Be = fem.divergence_element_matrices(D.G, D.vol)
     Ce = fem.stabilisation_element_matrices(D.G, D.vol, D.mu_e, D.h)
-    bnd = D.boundary
-    free_u = lambda v: ~bnd[v]
+    fixed = D.fixed
     Y = np.zeros((d + 1, len(verts)))
     E = D.elems
     for e in range(len(E)):
@@ -173,24 +178,25 @@ def sampled_stokes_rows(dim, n, inclusions, mu_table, verts, form, x):
             if va not in lookup:
                 continue
             i = lookup[va]
-            # velocity rows (zero on Dirichlet vertices)
-            if not bnd[va]:
-                src = Ke if (form != 'interface' or D.interface[va]) else Kl
-                for l in range(d):
-                    acc = 0.0
-                    for b in range(d + 1):
-                        vb = int(ev[b])
-                        if free_u(vb):
-                            for k in range(d):
-                                acc += src[e, a * d + l, b * d + k] * x[k * N + vb]
-                        acc += Be[e, b, a * d + l] * x[d * N + vb]
-                    Y[l, i] += acc
+            # velocity rows (zero for fixed components)
+            src = Ke if (form != 'interface' or D.interface[va] or D.boundary[va]) else Kl
+            for l in range(d):
+                if fixed[l, va]:
+                    continue
+                acc = 0.0
+                for b in range(d + 1):
+                    vb = int(ev[b])
+                    for k in range(d):
+                        if not fixed[k, vb]:
+                            acc += src[e, a * d + l, b * d + k] * x[k * N + vb]
+                    acc += Be[e, b, a * d + l] * x[d * N + vb]
+                Y[l, i] += acc
             # pressure row
             acc = 0.0
             for b in range(d + 1):
                 vb = int(ev[b])
-                if free_u(vb):
-                    for k in range(d):
+                for k in range(d):
+                    if not fixed[k, vb]:
                         acc += Be[e, a, b * d + k] * x[k * N + vb]
                 acc -= Ce[e, a, b] * x[d * N + vb]
             Y[d, i] += acc

@@ -61,6 +61,24 @@ def boundary_mask(dim, n):
     return np.any((ijk == 0) | (ijk == n), axis=1)
 
 
+def fixed_velocity(dim, n, bc='noslip'):
+    """Velocity components held at zero, shape (dim, N) bool (eq. boundary).
+
+    'noslip': homogeneous Dirichlet, every component of every boundary
+    vertex.  'freeslip': u . n = 0 on the faces of the unit cube / square,
+    i.e. component k of a vertex on a face with normal e_k (i_k = 0 or n);
+    the tangential components there are unknowns, and the zero tangential
+    traction is the natural condition of the weak form (no boundary term).
+    A vertex on an edge or corner has every normal of its faces fixed."""
+    ijk = vertex_ijk(dim, n)
+    on_face = (ijk == 0) | (ijk == n)                 # (N, dim)
+    if bc == 'noslip':
+        return np.repeat(np.any(on_face, axis=1)[None, :], dim, axis=0)
+    if bc == 'freeslip':
+        return on_face.T.copy()
+    raise ValueError(bc)
+
+
 def kuhn_offsets(dim):
     """The d! simplices of the unit cell as integer vertex offsets.
 

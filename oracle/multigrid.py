@@ -17,8 +17,8 @@ Readings taken where Sec. 5 leaves the choice open:
   * S_hat: delta solves (D_C + L_C) delta = B u - C p - g in the same colour
     order, then p += omega * delta.
   * transfers: prolongation is P1 interpolation between nested Kuhn
-    lattices, restriction its transpose; velocity entries of Dirichlet
-    vertices are zeroed after restriction.
+    lattices, restriction its transpose; fixed velocity entries are zeroed
+    after restriction.
   * coarse operators: rediscretisation with the centroid rule on each level,
     or with the volume-averaged fine viscosity (Galerkin for nested P1).
   * forms per level: the finest level uses the form of the call; the levels
@@ -145,13 +145,13 @@ def averaged_coarse_viscosity(dim, n_coarse, mu_f, imu_f, pure_values, table=Non
 
 
 class Level:
-    def __init__(self, dim, n, inclusions, mu_table, form, mu_e=None, imu_e=None):
-        self.disc = assemble.Discretisation(dim, n, inclusions, mu_table, mu_e=mu_e, imu_e=imu_e)
+    def __init__(self, dim, n, inclusions, mu_table, form, mu_e=None, imu_e=None, bc='noslip'):
+        self.disc = assemble.Discretisation(dim, n, inclusions, mu_table, mu_e=mu_e, imu_e=imu_e, bc=bc)
         d = self.disc
         self.dim, self.n, self.N = dim, n, d.N
         self.form = form
         self.A = d.velocity_operator(form)
-        D = sp.diags(np.tile(~d.boundary, dim).astype(np.float64))
+        D = sp.diags((~d.fixed.ravel()).astype(np.float64))
         self.B = (d.divergence() @ D).tocsr()
         self.BT = self.B.T.tocsr()
         self.C = d.stabilisation()
@@ -226,7 +226,7 @@ class Hierarchy:
 
     def __init__(self, dim, m, fine_level, coarse_level, inclusions, mu_table, form,
                  nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None, nu_inc=0,
-                 mid_form=None, table=None, coarse_rhs_mod=False):
+                 mid_form=None, table=None, coarse_rhs_mod=False, bc='noslip'):
         """coarse_mu: 'centroid' rediscretises every level with the centroid
         rule; 'average' uses averaged_coarse_viscosity below the finest
         level (``table``: its table-size model, None = exact averages).
@@ -239,7 +239,8 @@ class Hierarchy:
         form differs from the one above it, its momentum right-hand side
         r_1 is replaced by r_1 + B^T M^-1 r_2 with M the lumped
         (1/mu)-weighted pressure mass (Sec. 5, coarse grid solver; the
-        paper writes r_1 - B^T M^-1 r_2 for its opposite sign of B)."""
+        paper writes r_1 - B^T M^-1 r_2 for its opposite sign of B).
+        bc: 'noslip' or 'freeslip' on every level (mesh.fixed_velocity)."""
         self.dim = dim
         self.levels = {}
         self.P = {}
@@ -250,12 +251,12 @@ class Hierarchy:
             n = m * 2 ** l
             f = form if l == fine_level else (cform if l == coarse_level else mform)
             if l == fine_level or coarse_mu == 'centroid':
-                self.levels[l] = Level(dim, n, inclusions, mu_table, f)
+                self.levels[l] = Level(dim, n, inclusions, mu_table, f, bc=bc)
                 mu_f, imu_f = self.levels[l].disc.mu_e, self.levels[l].disc.imu_e
             else:
                 mu_f, imu_f, mq, iq = averaged_coarse_viscosity(dim, n, mu_f, imu_f, list(mu_table),
                                                                 table=table)
-                self.levels[l] = Level(dim, n, inclusions, mu_table, f, mu_e=mq, imu_e=iq)
+                self.levels[l] = Level(dim, n, inclusions, mu_table, f, mu_e=mq, imu_e=iq, bc=bc)
             if l > coarse_level:
                 self.P[l] = prolongation(dim, m * 2 ** (l - 1))
         self.fine, self.coarse = fine_level, coarse_level

@@ -21,8 +21,10 @@ def element_phase(dim, n, elems, inclusions):
 
     inclusions: list of dicts {'kind': 'sphere', 'center': c, 'radius': r,
     'phase': p} or {'kind': 'halfspace', 'axis': a, 'threshold': t,
-    'phase': p} (region x_a < t).  Strict inequalities: a centroid exactly
-    on a sphere or on the plane counts as outside.
+    'phase': p} (region x_a < t) or {'kind': 'box', 'lo': l, 'hi': h,
+    'phase': p} (region l_a < x_a < h_a on every axis).  Strict
+    inequalities: a centroid exactly on a sphere, plane or box face counts as
+    outside.
     """
     X = mesh.vertex_coords(dim, n)[elems]            # (E, d+1, d)
     cen = X.mean(axis=1)
@@ -34,6 +36,10 @@ def element_phase(dim, n, elems, inclusions):
             inside = np.sum((cen - c) ** 2, axis=1) < inc['radius'] ** 2
         elif inc['kind'] == 'halfspace':
             inside = cen[:, inc['axis']] < inc['threshold']
+        elif inc['kind'] == 'box':
+            lo = np.asarray(inc['lo'], dtype=np.float64)[:dim]
+            hi = np.asarray(inc['hi'], dtype=np.float64)[:dim]
+            inside = np.all((cen > lo) & (cen < hi), axis=1)
         else:
             raise ValueError(inc['kind'])
         new = inside & ~assigned

@@ -29,7 +29,7 @@ class IssError(RuntimeError):
 
 
 class Inclusion(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("phase", ctypes.c_int), ("a", ctypes.c_double * 4)]
+    _fields_ = [("kind", ctypes.c_int), ("phase", ctypes.c_int), ("a", ctypes.c_double * 6)]
 
 
 class Options(ctypes.Structure):
@@ -37,7 +37,10 @@ class Options(ctypes.Structure):
                 ("stab_beta", ctypes.c_double), ("outer", ctypes.c_int), ("restart", ctypes.c_int),
                 ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int),
                 ("mid_form", ctypes.c_int), ("merge_max_n", ctypes.c_int), ("spec_wide_min", ctypes.c_int),
-                ("cycles", ctypes.c_int), ("f16_rms", ctypes.c_double), ("coarse_rhs_mod", ctypes.c_int)]
+                ("cycles", ctypes.c_int), ("f16_rms", ctypes.c_double), ("coarse_rhs_mod", ctypes.c_int),
+                ("bc", ctypes.c_int)]
+
+BCS = {"noslip": 0, "freeslip": 1}
 
 
 # iss_launch_kind: smoother kernel shapes counted by iss_launch_counts
@@ -54,7 +57,7 @@ class SolveInfo(ctypes.Structure):
 
 
 EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "iss_num_vertices",
-           "iss_vertex_class", "iss_rhs_buoyancy", "iss_apply", "iss_residual", "iss_smooth",
+           "iss_vertex_class", "iss_rhs_buoyancy", "iss_rhs_nodal_force", "iss_apply", "iss_residual", "iss_smooth",
            "iss_restrict", "iss_prolong_add", "iss_coarse_solve", "iss_vcycle", "iss_solve",
            "iss_dot", "iss_last_error", "iss_net_create", "iss_net_destroy", "iss_net_info",
            "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
@@ -87,6 +90,7 @@ def lib():
     L.iss_num_vertices.argtypes = [vp, cint, ctypes.POINTER(i64)]
     L.iss_vertex_class.argtypes = [vp, cint, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.iss_rhs_buoyancy.argtypes = [vp, cint, ctypes.POINTER(cint), cint, cdbl, vp, vp]
+    L.iss_rhs_nodal_force.argtypes = [vp, cint, vp, vp, vp]
     L.iss_apply.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
     L.iss_residual.argtypes = [vp, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl), vp]
     L.iss_smooth.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
@@ -154,10 +158,15 @@ def inclusions_to_c(inclusions):
         if inc["kind"] == "sphere":
             c = list(inc["center"]) + [0.0] * (3 - len(inc["center"]))
             arr[i].kind, arr[i].phase = 0, int(inc["phase"])
-            arr[i].a[:] = [c[0], c[1], c[2], inc["radius"]]
+            arr[i].a[:] = [c[0], c[1], c[2], inc["radius"], 0.0, 0.0]
         elif inc["kind"] == "halfspace":
             arr[i].kind, arr[i].phase = 1, int(inc["phase"])
-            arr[i].a[:] = [float(inc["axis"]), inc["threshold"], 0.0, 0.0]
+            arr[i].a[:] = [float(inc["axis"]), inc["threshold"], 0.0, 0.0, 0.0, 0.0]
+        elif inc["kind"] == "box":
+            lo = list(inc["lo"]) + [0.0] * (3 - len(inc["lo"]))
+            hi = list(inc["hi"]) + [0.0] * (3 - len(inc["hi"]))
+            arr[i].kind, arr[i].phase = 2, int(inc["phase"])
+            arr[i].a[:] = [lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]]
         else:
             raise ValueError(inc["kind"])
     return arr
@@ -169,13 +178,14 @@ class Problem:
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
                  coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536, cycles=1,
-                 f16_rms=1.0 / 1024.0, coarse_rhs_mod=False, elem_phase=None):
+                 f16_rms=1.0 / 1024.0, coarse_rhs_mod=False, elem_phase=None, bc="noslip"):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
                       -1 if coarse_form is None else FORMS[coarse_form], nu_inc,
                       -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min, cycles, f16_rms,
-                      int(bool(coarse_rhs_mod)))
+                      int(bool(coarse_rhs_mod)), BCS[bc])
+        self.bc = bc
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()
         self._h = None
@@ -191,6 +201,8 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w, **kw):
+        if "bc" in w:
+            kw.setdefault("bc", w["bc"])
         return cls(w["dim"], w["macro"], w["levels"], w["coarse"], w["inclusions"], w["mu"], **kw)
 
     @classmethod
@@ -259,6 +271,18 @@ class Problem:
         ph = (ctypes.c_int * max(1, len(phases)))(*phases)
         _check(lib().iss_rhs_buoyancy(self._h, level, ph, len(phases), rho,
                                       self._vec(b, level, torch.float64), _stream()))
+        return b
+
+    def rhs_nodal_force(self, f, b, level=None):
+        """b = (M f_1 | .. | M f_d | 0) from nodal force values f (FP64
+        device tensor of d N entries)."""
+        import torch
+        level = self.levels if level is None else level
+        if not (isinstance(f, torch.Tensor) and f.is_cuda and f.is_contiguous() and f.dtype == torch.float64
+                and f.numel() == self.dim * self.num_vertices(level)):
+            raise ValueError("f must be a contiguous FP64 CUDA tensor of dim * N entries")
+        _check(lib().iss_rhs_nodal_force(self._h, level, ctypes.c_void_p(f.data_ptr()),
+                                         self._vec(b, level, torch.float64), _stream()))
         return b
 
     def apply(self, form, x, y, level=None, block="full"):

@@ -347,8 +347,11 @@ int element_phase(const iss_problem* p, const double (&c)[3]) {
             double r2 = 0;
             for (int a = 0; a < p->dim; ++a) r2 += (c[a] - in.a[a]) * (c[a] - in.a[a]);
             inside = r2 < in.a[3] * in.a[3];
-        } else {
+        } else if (in.kind == ISS_HALFSPACE) {
             inside = c[(int)in.a[0]] < in.a[1];
+        } else {
+            inside = true;
+            for (int a = 0; a < p->dim; ++a) inside = inside && c[a] > in.a[2 * a] && c[a] < in.a[2 * a + 1];
         }
         if (inside) return in.phase;
     }
@@ -665,6 +668,7 @@ int setup_level(iss_problem* p, int l) {
     V.merge_max_n = p->opt.merge_max_n;
     V.spec_wide_min = p->opt.spec_wide_min;
     V.launch_count = p->launch_count;
+    V.freeslip = p->opt.bc == ISS_BC_FREESLIP;
     return ISS_OK;
 }
 
@@ -692,6 +696,18 @@ void split_buffers(iss_problem* p, int l, int prec, void** xs, void** bs, void**
 }
 
 // ----------------------------------------------------------------------------
+// velocity component f of vertex v (lattice of n cells per axis) is fixed:
+// every component on the boundary for no-slip, the normal one on each face
+// for free-slip (eq. boundary)
+bool velocity_fixed(const iss_problem* p, int n, int64_t v, int f) {
+    const int64_t n1 = n + 1;
+    int ijk[3] = {(int)(v % n1), (int)((v / n1) % n1), p->dim == 3 ? (int)(v / (n1 * n1)) : 0};
+    if (p->opt.bc == ISS_BC_FREESLIP) return ijk[f] == 0 || ijk[f] == n;
+    for (int a = 0; a < p->dim; ++a)
+        if (ijk[a] == 0 || ijk[a] == n) return true;
+    return false;
+}
+
 // coarse level: dense bordered matrix, LU with partial pivoting, inverse
 
 template <int D>
@@ -704,12 +720,13 @@ void coarse_matrix(const iss_problem* p, int form, std::vector<double>& Kd, int6
     const Level& L = p->lv[p->coarse];
     const int n = L.v.n;
     const int64_t n1 = n + 1, N = L.v.N;
-    // compact numbering of free dofs: velocity of interior vertices, all pressure
+    // compact numbering of free dofs: the velocity components that are not
+    // fixed by the boundary condition, every pressure
     std::vector<int64_t> cmap((size_t)(D + 1) * N, -1);
     free_idx.clear();
     for (int f = 0; f <= D; ++f)
         for (int64_t v = 0; v < N; ++v)
-            if (f == D || !(L.cls[v] & 2)) {
+            if (f == D || !velocity_fixed(p, n, v, f)) {
                 cmap[(size_t)f * N + v] = (int64_t)free_idx.size();
                 free_idx.push_back((int32_t)((int64_t)f * N + v));
             }
@@ -1301,6 +1318,7 @@ int iss_default_options(iss_options* o) {
     o->cycles = 1;
     o->f16_rms = 1.0 / 1024.0;
     o->coarse_rhs_mod = 0;
+    o->bc = ISS_BC_NOSLIP;
     return ISS_OK;
 }
 
@@ -1358,7 +1376,8 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
     for (int i = 0; i < ninclusions; ++i) {
         const auto& in = inclusions[i];
         if (in.phase < 0 || in.phase >= nphase) return fail(ISS_E_INVAL, "inclusion phase out of range");
-        if (in.kind != ISS_SPHERE && in.kind != ISS_HALFSPACE) return fail(ISS_E_INVAL, "bad inclusion kind");
+        if (in.kind != ISS_SPHERE && in.kind != ISS_HALFSPACE && in.kind != ISS_BOX)
+            return fail(ISS_E_INVAL, "bad inclusion kind");
         if (in.kind == ISS_HALFSPACE && (in.a[0] < 0 || (int)in.a[0] >= dim))
             return fail(ISS_E_INVAL, "half-space axis out of range");
     }
@@ -1396,7 +1415,8 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
         (p->opt.coarse_mu != ISS_COARSE_MU_CENTROID && p->opt.coarse_mu != ISS_COARSE_MU_AVERAGE) ||
         p->opt.coarse_form < -1 || p->opt.coarse_form > 2 || p->opt.mid_form < -1 || p->opt.mid_form > 2 ||
         p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0 || p->opt.cycles < 1 || p->opt.cycles > 16 ||
-        !(p->opt.f16_rms > 0) || !(p->opt.f16_rms < 65504.0)) {
+        !(p->opt.f16_rms > 0) || !(p->opt.f16_rms < 65504.0) ||
+        (p->opt.bc != ISS_BC_NOSLIP && p->opt.bc != ISS_BC_FREESLIP)) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }
@@ -1522,6 +1542,18 @@ int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
     vol /= (p->dim == 3 ? 6.0 : 2.0);
     ISS_HIP(k_rhs_buoyancy(L.v, p->d_flag, rho, vol, b, s));
     ISS_HIP(hipStreamSynchronize(s));   // flag buffer is reused by the next call
+    return ISS_OK;
+}
+
+int iss_rhs_nodal_force(iss_problem* p, int level, const double* f, double* b, iss_stream_t stream) {
+    if (!p || !f || !b) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_level(p, level))) return rc;
+    const Level& L = p->lv[level];
+    double vol = 1.0;
+    for (int a = 0; a < p->dim; ++a) vol /= L.v.n;
+    vol /= (p->dim == 3 ? 6.0 : 2.0);
+    ISS_HIP(k_rhs_nodal_force(L.v, f, vol, b, (hipStream_t)stream));
     return ISS_OK;
 }
 
@@ -1792,6 +1824,7 @@ int iss_net_create(iss_problem* p, iss_net** out) {
     if (!p || !out) return fail(ISS_E_INVAL, "null argument");
     *out = nullptr;
     if (p->dim != 3) return fail(ISS_E_INVAL, "the band correction network is 3D only");
+    if (p->opt.bc != ISS_BC_NOSLIP) return fail(ISS_E_INVAL, "the band correction network is trained for no-slip");
     const Level& L = p->lv[p->levels];
     const int n = L.v.n;
     const int64_t n1 = n + 1, N = L.v.N;

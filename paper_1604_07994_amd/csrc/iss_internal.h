@@ -45,6 +45,8 @@ struct LevelView {
     int merge_max_n;
     int64_t spec_wide_min;
     int64_t* launch_count;   // host counters per iss_launch_kind, or null
+    int freeslip;            // 0: no-slip (every boundary velocity fixed);
+                             // 1: free-slip (the normal component fixed)
 };
 
 enum { SPLIT_PACK = 0, SPLIT_UNPACK = 1 };
@@ -129,6 +131,8 @@ hipError_t k_dense_matvec(const double* A, int64_t m, const double* x, double* y
                           hipStream_t s);
 hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* buoyant_flag, double rho,
                           double vol_unit, double* b, hipStream_t s);
+// b = (M f_1 | .. | M f_d | 0), fixed velocity entries zero; vol = |T|
+hipError_t k_rhs_nodal_force(const LevelView& L, const double* f, double vol, double* b, hipStream_t s);
 
 // ---- learned band correction (iss_net.hip)
 struct NetImpl;

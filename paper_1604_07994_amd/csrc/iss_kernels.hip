@@ -187,6 +187,14 @@ __device__ __forceinline__ bool on_boundary(const LevelView& L, const int (&ijk)
     return b;
 }
 
+// velocity component l of the vertex is fixed (eq. boundary): every
+// component of a boundary vertex for no-slip, the normal component on each
+// face for free-slip
+template <int D>
+__device__ __forceinline__ bool vel_fixed(const LevelView& L, const int (&ijk)[3], int l) {
+    return L.freeslip ? (ijk[l] == 0 || ijk[l] == L.n) : on_boundary<D>(L, ijk);
+}
+
 // ----------------------------------------------------------------------------
 // element loop of one special vertex: rows of A (form F), B^T, B and C.
 
@@ -407,9 +415,8 @@ __device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s
     const int64_t v = L.spec[s];
     int ijk[3];
     vertex_ijk<D>(L, v, ijk);
-    const bool bnd = on_boundary<D>(L, ijk);
-    if (bnd) {
-        // Dirichlet velocity rows are zero; only the (truncated) pressure
+    if (!L.freeslip && on_boundary<D>(L, ijk)) {
+        // no-slip velocity rows are zero; only the (truncated) pressure
         // row of the full operator is formed
         C out[D + 1];
 #pragma unroll
@@ -433,21 +440,26 @@ __device__ __forceinline__ void apply_special_body(const LevelView& L, int64_t s
         }
         return;
     }
+    // interface rows, and free-slip boundary rows (the full rows of the
+    // form on Gamma_F, Sec. 2.2) with their normal component fixed
     C U[D][NB], P[1][NB];
     load_guarded<D, D, T, C>(L, x, v, ijk, 0, U);
     load_guarded<D, 1, T, C>(L, x, v, ijk, D, P);
     RowAcc<D, F, true, BLK == BLOCK_FULL, C> r;
     element_rows<D, F, true, BLK == BLOCK_FULL, false, false, C>(L, s, U, P[0], P[0], r);
+    bool fix[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) fix[l] = vel_fixed<D>(L, ijk, l);
     C out[D + 1];
 #pragma unroll
     for (int l = 0; l < D; ++l)
-        out[l] = bnd ? (C)0 : (C)L.sA * r.au[l] + (BLK == BLOCK_FULL ? (C)L.sB * r.abt[l] : (C)0);
+        out[l] = fix[l] ? (C)0 : (C)L.sA * r.au[l] + (BLK == BLOCK_FULL ? (C)L.sB * r.abt[l] : (C)0);
     out[D] = (BLK == BLOCK_FULL) ? (C)L.sB * r.bdiv - (C)L.sC * r.cp : (C)0;
 #pragma unroll
     for (int f = 0; f <= D; ++f) {
         const int64_t e = (int64_t)f * L.N + v;
         if (MODE == MODE_RESID) {
-            const bool zero = (f < D && bnd) || (f == D && BLK != BLOCK_FULL);
+            const bool zero = (f < D && fix[f < D ? f : 0]) || (f == D && BLK != BLOCK_FULL);
             y[e] = zero ? (T)0.0f : (T)((C)b[e] - out[f]);
         } else {
             y[e] = (T)out[f];
@@ -1201,7 +1213,8 @@ __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colo
     if (sp >= L.spec_off[colour + 1]) return;
     int ijk[3];
     vertex_ijk<D>(L, L.spec[sp], ijk);
-    if (on_boundary<D>(L, ijk)) return;          // Dirichlet velocity
+    const bool bnd = on_boundary<D>(L, ijk);
+    if (bnd && !L.freeslip) return;              // no-slip: every component fixed
     const int64_t v = sidx<D>(L, ijk[0], ijk[1], ijk[2]);
     C U[D][NB], P[1][NB];
     load_guarded_split<D, D, T, C>(L, xs, ijk, 0, U);
@@ -1214,6 +1227,18 @@ __device__ __forceinline__ void gs_vel_special_body(const LevelView& L, int colo
         res[l] = (C)bs[(int64_t)l * L.Ns + v] - (C)L.sB * r.abt[l] - (C)L.sA * r.au[l];
 #pragma unroll
         for (int k = 0; k < D; ++k) Dm[l][k] = (C)L.sA * r.Dm[l][k];
+    }
+    if (bnd) {
+        // free-slip: a fixed (normal) component keeps its zero; its row and
+        // column leave the point block
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            if (!vel_fixed<D>(L, ijk, l)) continue;
+            res[l] = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) { Dm[l][k] = 0; Dm[k][l] = 0; }
+            Dm[l][l] = 1;
+        }
     }
     block_gs_update<D, F, BWD, C>(res, Dm, du);
 #pragma unroll
@@ -1409,7 +1434,6 @@ __global__ __launch_bounds__(256) void k_restrict_t(LevelView Lf, LevelView Lc,
     if (I >= Lc.N) return;
     int c[3];
     vertex_ijk<D>(Lc, I, c);
-    const bool bnd = on_boundary<D>(Lc, c);
     const int64_t F = 2 * c[0] + 2 * c[1] * Lf.sy + 2 * c[2] * Lf.sz;
     C acc[D + 1];
 #pragma unroll
@@ -1428,7 +1452,8 @@ __global__ __launch_bounds__(256) void k_restrict_t(LevelView Lf, LevelView Lc,
         for (int f = 0; f <= D; ++f) acc[f] += (C)0.5 * (C)rf[(int64_t)f * Lf.N + fo];
     }
 #pragma unroll
-    for (int f = 0; f <= D; ++f) rc[(int64_t)f * Lc.N + I] = (f < D && bnd) ? (T)0.0f : (T)acc[f];
+    for (int f = 0; f <= D; ++f)
+        rc[(int64_t)f * Lc.N + I] = (f < D && vel_fixed<D>(Lc, c, f < D ? f : 0)) ? (T)0.0f : (T)acc[f];
 }
 
 template <int D, typename T>
@@ -1836,7 +1861,46 @@ __global__ __launch_bounds__(256) void k_buoyancy_special(LevelView L, const uin
         const int ph = L.spec_eph[s * NS + sl];
         if (ph != OUTSIDE && flag[ph]) acc += vol;
     }
-    b[(int64_t)(D - 1) * L.N + v] = on_boundary<D>(L, ijk) ? 0.0 : -rho * acc / (D + 1);
+    b[(int64_t)(D - 1) * L.N + v] = vel_fixed<D>(L, ijk, D - 1) ? 0.0 : -rho * acc / (D + 1);
+}
+
+// Load of a nodal body force: b_k = M f_k, M the P1 mass matrix (entries
+// |T| (1 + delta_ab) / ((d+1)(d+2)) on each simplex T), one vertex per
+// thread summing over the incident elements that lie in the domain.
+template <int D>
+__global__ __launch_bounds__(256) void k_nodal_force(LevelView L, const double* __restrict__ f,
+                                                     double vol, double* __restrict__ b) {
+    constexpr int NS = KuhnTables<D>::NS;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= L.N) return;
+    int ijk[3];
+    vertex_ijk<D>(L, v, ijk);
+    double acc[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] = 0;
+    static_for<0, NS>([&](auto slc) {
+        constexpr int sl = decltype(slc)::value;
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int c = ijk[a] + Kuhn<D>::T.slot_cell[sl][a];
+            in = in && c >= 0 && c < L.n;
+        }
+        if (!in) return;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double sum = f[(int64_t)k * L.N + v];          // the diagonal's second half
+            static_for<0, D + 1>([&](auto bc) {
+                constexpr int o = Kuhn<D>::T.slot_nb[sl][decltype(bc)::value];
+                sum += f[(int64_t)k * L.N + v + nb_lin<D>(L, o)];
+            });
+            acc[k] += sum;
+        }
+    });
+    const double w = vol / ((D + 1) * (D + 2));
+#pragma unroll
+    for (int k = 0; k < D; ++k) b[(int64_t)k * L.N + v] = vel_fixed<D>(L, ijk, k) ? 0.0 : w * acc[k];
+    b[(int64_t)D * L.N + v] = 0.0;
 }
 
 // ----------------------------------------------------------------------------
@@ -2261,6 +2325,12 @@ hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* flag, double rho, d
         if (nb > 0) hipLaunchKernelGGL(k_buoyancy_bulk<2>, dim3((unsigned)nb), dim3(BX, BY), 0, s, L, flag, rho, vol, b);
         if (ns > 0) hipLaunchKernelGGL(k_buoyancy_special<2>, grid1(ns), dim3(256), 0, s, L, flag, rho, vol, b);
     }
+    return hipGetLastError();
+}
+
+hipError_t k_rhs_nodal_force(const LevelView& L, const double* f, double vol, double* b, hipStream_t s) {
+    if (L.dim == 3) hipLaunchKernelGGL(k_nodal_force<3>, grid1(L.N), dim3(256), 0, s, L, f, vol, b);
+    else hipLaunchKernelGGL(k_nodal_force<2>, grid1(L.N), dim3(256), 0, s, L, f, vol, b);
     return hipGetLastError();
 }
 
