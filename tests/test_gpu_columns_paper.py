@@ -102,3 +102,27 @@ def test_gradient_form_keeps_an_inconsistency(differences):
         for key in ("l2", "V"):
             ratio = differences[("gradient", l)][key] / paper[str(l)][key]
             assert 0.25 <= ratio <= 4.0, (l, key, ratio)
+
+
+@pytest.mark.parametrize("form", ["interface", "strain", "gradient"])
+def test_columns_rates_in_the_paper_configuration(form):
+    """Sec. 5 multigrid on the columns problem (33^3 over 9^3): V(3,3) with
+    two more steps per coarser level, omega 0.3, the strain form on the
+    coarsest level with the modified momentum right-hand side.  The
+    asymptotic rate (200 rescaled cycles) stays in the paper's range
+    (0.24-0.30 at levels 5-8) below 0.35; for the interface and gradient
+    forms the naive swap (no modification) is slower."""
+    import torch
+    from paper_1604_07994_amd import Problem
+    w = small_workload("columns_3d", 3)
+    x0 = to_dev(iss_inputs.random_vector(3, w["n"], seed=157, bc="freeslip"))
+    kw = dict(outer="richardson", omega=0.3, nu1=3, nu2=3, nu_inc=2, coarse_mu="average", coarse_form="strain")
+    P = Problem.from_workload(w, coarse_rhs_mod=True, **kw)
+    rate = P.asymptotic_rate(form, x0.clone(), iters=200)[-1]
+    P.close()
+    assert rate < 0.35, (form, rate)
+    if form != "strain":
+        Pn = Problem.from_workload(w, **kw)
+        naive = Pn.asymptotic_rate(form, x0.clone(), iters=200)[-1]
+        Pn.close()
+        assert naive > rate + 0.02, (form, rate, naive)
