@@ -130,20 +130,27 @@ def measured_traffic(kernel, form):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
     reading for a plain copy of known size), or None when the kernel source
-    has changed since the counters were taken."""
+    or the host layout code has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_1604_07994_amd", "csrc", "iss_kernels.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
     entry = rec.get("%s/%s" % (kernel, form))
-    if not entry or rec.get("iss_kernels_sha256") != digest:
+    if not entry or rec.get("sources_sha256") != kernel_sources_digest():
         return None
     return entry["bytes_per_launch"]
+
+
+def kernel_sources_digest():
+    """SHA-256 over the kernel source and the host source that fixes the
+    data layout the kernels stream (the counters are valid for both)."""
+    h = hashlib.sha256()
+    for name in ("iss_kernels.hip", "iss_host.cpp"):
+        with open(os.path.join(ROOT, "paper_1604_07994_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 # Sec. 5, Table timeANDconv: time of one V_var(3,3) cycle and asymptotic
