@@ -166,6 +166,15 @@ typedef struct {
                            * rows of the form (a_tr for ISS_INTERFACE, as
                            * Sec. 2.2 requires on Gamma_F).  Not with the
                            * learned band correction (iss_net_create). */
+    int split_align;      /* kernel shape (results equal up to rounding
+                           * order): the colour-split layout of the smoother
+                           * stores each colour run of a row in q entries,
+                           * q >= ceil((n+1)/(d+1)).  0 (default): q is
+                           * rounded up to a multiple of 16 (FP64 runs on
+                           * 128-byte lines) or else of 8 where that adds
+                           * at most a quarter, otherwise unpadded; a value
+                           * 1..64 rounds q up to a multiple of it on every
+                           * level. */
 } iss_options;
 
 typedef struct {

@@ -548,9 +548,11 @@ void averaged_viscosity(iss_problem* p, int l) {
 // else of 8 (64-byte sectors) where that adds at most a quarter.  Aligned
 // runs keep a colour phase's reads and its run writes off lines shared with
 // other runs: the FP64 velocity colour phase at 257^3 (q 65 -> 80) takes
-// 95 instead of 109 us.  Small levels keep q unpadded.
-int split_run_length(int64_t n1, int M) {
+// 95 instead of 109 us.  Small levels keep q unpadded.  align > 0 (option
+// split_align) forces a multiple of align instead.
+int split_run_length(int64_t n1, int M, int align) {
     const int64_t q = (n1 + M - 1) / M;
+    if (align > 0) return (int)((q + align - 1) / align * align);
     for (int pad : {16, 8}) {
         const int64_t qp = (q + pad - 1) / pad * pad;
         if (4 * qp <= 5 * q) return (int)qp;
@@ -642,7 +644,7 @@ int setup_level(iss_problem* p, int l) {
     if ((rc = dev_upload(p, &L.d_vphase, vphase.data(), vphase.size()))) return rc;
     // colour-split layout of the smoother: rows grouped by i mod (d+1)
     constexpr int M = D + 1;
-    const int q = split_run_length(n1, M);
+    const int q = split_run_length(n1, M, p->opt.split_align);
     const int64_t Rp = (int64_t)M * q;
     const int64_t Pp = Rp * n1;
     const int64_t Ns = (D == 3) ? Pp * n1 : Rp * n1;
@@ -1334,6 +1336,7 @@ int iss_default_options(iss_options* o) {
     o->f16_rms = 1.0 / 1024.0;
     o->coarse_rhs_mod = 0;
     o->bc = ISS_BC_NOSLIP;
+    o->split_align = 0;
     return ISS_OK;
 }
 
@@ -1379,7 +1382,7 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
     {
         // the smoother addresses a split-layout field through 32-bit byte
         // offsets: every FP64 field must stay below 4 GiB
-        const int64_t q = split_run_length(n + 1, dim + 1);
+        const int64_t q = split_run_length(n + 1, dim + 1, opt ? opt->split_align : 0);
         const int64_t Ns = (int64_t)(dim + 1) * q * (dim == 3 ? (n + 1) * (n + 1) : (n + 1));
         if (Ns * (int64_t)sizeof(double) >= (int64_t)1 << 32)
             return fail(ISS_E_INVAL, "problem too large: a split-layout field exceeds 4 GiB");
@@ -1431,7 +1434,8 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
         p->opt.coarse_form < -1 || p->opt.coarse_form > 2 || p->opt.mid_form < -1 || p->opt.mid_form > 2 ||
         p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0 || p->opt.cycles < 1 || p->opt.cycles > 16 ||
         !(p->opt.f16_rms > 0) || !(p->opt.f16_rms < 65504.0) ||
-        (p->opt.bc != ISS_BC_NOSLIP && p->opt.bc != ISS_BC_FREESLIP)) {
+        (p->opt.bc != ISS_BC_NOSLIP && p->opt.bc != ISS_BC_FREESLIP) || p->opt.split_align < 0 ||
+        p->opt.split_align > 64) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }

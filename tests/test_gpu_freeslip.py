@@ -10,7 +10,8 @@ oracle is assembled with the same fixed set (mesh.fixed_velocity).
 Tolerances as for the no-slip tests: applies and residuals 1e-12 of
 max(|K| |x|), smoothing steps 1e-11 and V-cycles 1e-10 of max |x|, the force
 load 1e-14 of max |b| (a sum of at most 24 x 5 products).  Both kernel
-shapes run (merged launches; large-level launches with merge_max_n = 0)."""
+shapes run (merged launches; large-level launches with merge_max_n = 0,
+also with every colour run padded to 16 entries, split_align = 16)."""
 import numpy as np
 import pytest
 
@@ -21,7 +22,7 @@ from tests.gpu_common import abs_scale, assert_close_scaled, gpu_problem, small_
 pytestmark = pytest.mark.gpu
 
 CASES = [("columns_3d", 2, 2), ("columns_3d", 2, 4), ("square_split_2d", 5, None)]
-PATHS = {"merged": {}, "large": dict(merge_max_n=0)}
+PATHS = {"merged": {}, "large": dict(merge_max_n=0), "large-aligned": dict(merge_max_n=0, split_align=16)}
 
 
 def _workload(name, levels, macro):

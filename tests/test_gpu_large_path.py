@@ -7,8 +7,10 @@ k_p_rhs_z, which also finishes colour 0; k_vel_rhs_s and k_p_rhs_g in 2D),
 k_gs_vel_s, k_gs_vel_special_s, k_gs_p_s and k_gs_p_special_s in one-wave or
 256-thread workgroups; the bulk rows of applies and residuals take the
 LDS-tiled k_apply_z in 3D.  Smaller levels use merged launches.  The option merge_max_n = 0 selects the large-level
-kernels on every level and spec_wide_min = 0 sends every pressure special
-list to the 256-thread kernel, so these kernels are compared with the
+kernels on every level, spec_wide_min = 0 sends every pressure special
+list to the 256-thread kernel and split_align = 16 pads every colour run of
+the split layout to a multiple of 16 entries (the automatic padding of the
+large levels, here at small sizes), so these kernels are compared with the
 oracle here at sizes the oracle handles (17^3 to 33^3, 33^2, a ragged
 25^3), and the host launch counters show which kernels ran.
 
@@ -31,7 +33,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = [("square_split_2d", 5, None), ("sphere_3d", 4, None), ("sinker_3d", 4, None),
          ("sphere_3d", 3, 3)]
-PATHS = {"large": dict(merge_max_n=0), "large-wide": dict(merge_max_n=0, spec_wide_min=0)}
+PATHS = {"large": dict(merge_max_n=0), "large-wide": dict(merge_max_n=0, spec_wide_min=0),
+         "large-aligned": dict(merge_max_n=0, split_align=16)}
 PARAMS = list(itertools.product(CASES, sorted(PATHS)))
 
 
