@@ -27,7 +27,8 @@ Readings taken where Sec. 5 leaves the choice open:
     swap to the strain form on the coarse grid of Sec. 5.
   * coarse solve: direct, on the free dofs bordered by the pressure
     constraint sum_j w_j p_j = 0 (a direct coarse solver is the case the
-    paper calls unproblematic, Sec. 5).
+    paper calls unproblematic, Sec. 5), or the preconditioned MINRES of
+    Sec. 5 (krylov.py).
   * cycle: V(3,3) on every level ("V_var" is not defined further).
   * stopping: Euclidean norm of b - K x over all dofs <= rtol * ||b||.
 """
@@ -226,7 +227,8 @@ class Hierarchy:
 
     def __init__(self, dim, m, fine_level, coarse_level, inclusions, mu_table, form,
                  nu1=3, nu2=3, omega=OMEGA, coarse_mu='centroid', coarse_form=None, nu_inc=0,
-                 mid_form=None, table=None, coarse_rhs_mod=False, bc='noslip'):
+                 mid_form=None, table=None, coarse_rhs_mod=False, bc='noslip', coarse_solver='direct',
+                 minres_iters=30, cg_iters=5):
         """coarse_mu: 'centroid' rediscretises every level with the centroid
         rule; 'average' uses averaged_coarse_viscosity below the finest
         level (``table``: its table-size model, None = exact averages).
@@ -240,7 +242,10 @@ class Hierarchy:
         r_1 is replaced by r_1 + B^T M^-1 r_2 with M the lumped
         (1/mu)-weighted pressure mass (Sec. 5, coarse grid solver; the
         paper writes r_1 - B^T M^-1 r_2 for its opposite sign of B).
-        bc: 'noslip' or 'freeslip' on every level (mesh.fixed_velocity)."""
+        bc: 'noslip' or 'freeslip' on every level (mesh.fixed_velocity).
+        coarse_solver: 'direct' (bordered dense LU) or 'minres' (the
+        block-diagonally preconditioned MINRES of Sec. 5, krylov.py, with
+        minres_iters outer and cg_iters inner Jacobi-CG steps)."""
         self.dim = dim
         self.levels = {}
         self.P = {}
@@ -260,7 +265,13 @@ class Hierarchy:
             if l > coarse_level:
                 self.P[l] = prolongation(dim, m * 2 ** (l - 1))
         self.fine, self.coarse = fine_level, coarse_level
-        self.coarse_solver = CoarseSolver(self.levels[coarse_level])
+        if coarse_solver == 'direct':
+            self.coarse_solver = CoarseSolver(self.levels[coarse_level])
+        elif coarse_solver == 'minres':
+            from . import krylov
+            self.coarse_solver = krylov.MinresCoarseSolver(self.levels[coarse_level], minres_iters, cg_iters)
+        else:
+            raise ValueError(coarse_solver)
         self.nu1, self.nu2, self.omega, self.nu_inc = nu1, nu2, omega, nu_inc
         self.coarse_rhs_mod = (coarse_rhs_mod and fine_level > coarse_level and
                                self.levels[coarse_level].form != self.levels[coarse_level + 1].form)
