@@ -164,25 +164,34 @@ PAPER_COLUMNS_L6 = {"strain": {"cycle_s": 3.02, "rate": 0.280},
 def columns_report(rate_iters, reps=5):
     """The paper's timing problem: viscosity columns (mu 1 / 10, free-slip)
     at 257^3 with its multigrid settings (Uzawa V(3,3) with 2 more steps per
-    coarser level, omega 0.3, the strain form on the coarsest level with the
-    momentum right-hand side modified by B^T M^-1 r_2, averaged coarse
-    viscosity): per form the time of one V-cycle (HIP events), the
-    asymptotic rate and the stationary iterations to 1e-8 from zero."""
+    coarser level, omega 0.3, averaged coarse viscosity, its coarse grid at
+    level 2 solved by preconditioned MINRES, for a_tr in the strain form with
+    the momentum right-hand side modified by B^T M^-1 r_2):
+    per form the time of one V-cycle (HIP events), the asymptotic rate and
+    the stationary iterations to 1e-8 from zero; then cycle time and rate
+    with the hierarchy continued to a 9^3 direct coarse solve."""
     import numpy as np
     import torch
     import iss_inputs
     from paper_1604_07994_amd import Problem
     w = iss_inputs.workload("columns_3d")
-    P = Problem.from_workload(w, outer="richardson", omega=0.3, nu1=3, nu2=3, nu_inc=2, coarse_mu="average",
-                              coarse_form="strain", coarse_rhs_mod=True)
+    # the paper's coarse grid: level 2 (17^3, 19 652 unknowns), MINRES there;
+    # a_tr is swapped for the strain form there (with the modified right-hand
+    # side), the strain and gradient forms keep their own
+    wp = dict(w, coarse=2)
+    base = dict(outer="richardson", omega=0.3, nu1=3, nu2=3, nu_inc=2, coarse_mu="average")
     dev = torch.device("cuda:0")
-    f = torch.from_numpy(np.ascontiguousarray(iss_inputs.column_force(3, w["n"]).ravel())).to(dev)
-    b = torch.empty(P.vector_size(), dtype=torch.float64, device=dev)
-    P.rhs_nodal_force(f, b)
-    del f
+    fn = torch.from_numpy(np.ascontiguousarray(iss_inputs.column_force(3, w["n"]).ravel())).to(dev)
     x0 = torch.from_numpy(iss_inputs.random_vector(3, w["n"], seed=8, bc="freeslip")).to(dev)
     out, sol = {}, {}
+    P = None
     for form in ("interface", "strain", "gradient"):
+        if P is not None:
+            P.close()
+        swap = dict(coarse_form="strain", coarse_rhs_mod=True) if form == "interface" else {}
+        P = Problem.from_workload(wp, coarse_solver="minres", minres_iters=30, minres_cg=5, **base, **swap)
+        b = torch.empty(P.vector_size(), dtype=torch.float64, device=dev)
+        P.rhs_nodal_force(fn, b)
         x = torch.zeros_like(b)
         P.vcycle(form, x, b)
         ms = event_time(lambda: P.vcycle(form, x, b), reps)
@@ -216,10 +225,25 @@ def columns_report(rate_iters, reps=5):
                                       "paper_l2": paper_tab[form][0], "paper_V": paper_tab[form][1]}
     log("columns differences to the strain solution: %s" % diffs)
     P.close()
+    # the same multigrid continued to a 9^3 level solved directly
+    direct = {}
+    for form in ("interface", "strain", "gradient"):
+        swap = dict(coarse_form="strain", coarse_rhs_mod=True) if form == "interface" else {}
+        Pd = Problem.from_workload(w, **base, **swap)
+        x = torch.zeros_like(b)
+        Pd.vcycle(form, x, b)
+        ms = event_time(lambda: Pd.vcycle(form, x, b), reps)
+        hist = Pd.asymptotic_rate(form, x0.clone(), iters=rate_iters) if rate_iters > 0 else [float("nan")]
+        direct[form] = {"cycle_ms": ms, "rate": hist[-1]}
+        Pd.close()
+    log("columns, 9^3 direct coarse solve: %s" % direct)
     return {"workload": "columns_3d: 257^3 vertices, mu 1 / 10 columns (0,1/4)^2 x (0,1) and (3/4,1)^2 x (0,1), "
                         "free-slip, f = (0, 0, -cos 2 pi x cos 2 pi y sin pi z)",
-            "cycle": "Uzawa V(3,3) +2 steps per coarser level, omega 0.3, averaged coarse viscosity, strain form "
-                     "on the coarsest level (9^3) with the modified momentum right-hand side, FP64",
+            "cycle": "Uzawa V(3,3) +2 steps per coarser level, omega 0.3, averaged coarse viscosity, FP64; "
+                     "coarsest level 17^3 (the paper's level 2) solved by 30 MINRES steps preconditioned with 5 "
+                     "Jacobi-CG steps and the lumped pressure mass, in the strain form with the modified "
+                     "momentum right-hand side for the interface form, in their own form for the others",
+            "direct_coarse_9": direct,
             "forms": out,
             "strain_over_interface_cycle": out["strain"]["cycle_ms"] / out["interface"]["cycle_ms"],
             "solution_differences_level6": diffs}

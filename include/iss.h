@@ -35,7 +35,8 @@
  *
  * Memory ownership.  Vector arguments are device pointers owned by the
  * caller (any allocator; 8-byte aligned).  The library allocates and owns
- * its metadata (hipMalloc at create time) and the coarse factorisation.
+ * its metadata (hipMalloc at create time) and the coarse factorisation or
+ * the coarse Krylov vectors (at their first use).
  * Its work vectors (per-level V-cycle and smoother buffers, the FGMRES
  * basis) come from a workspace the caller binds with iss_bind_workspace,
  * or, if none is bound, from hipMalloc at their first use; iss_problem_
@@ -80,6 +81,7 @@ enum iss_prec { ISS_FP64 = 0, ISS_FP32 = 1, ISS_FP32_BF16STORE = 2, ISS_FP32_FP1
 enum iss_outer { ISS_OUTER_RICHARDSON = 0, ISS_OUTER_FGMRES = 1 };
 enum iss_inclusion_kind { ISS_SPHERE = 0, ISS_HALFSPACE = 1, ISS_BOX = 2 };
 enum iss_bc { ISS_BC_NOSLIP = 0, ISS_BC_FREESLIP = 1 };
+enum iss_coarse_solver { ISS_COARSE_DIRECT = 0, ISS_COARSE_MINRES = 1 };
 enum iss_coarse_mu { ISS_COARSE_MU_CENTROID = 0, ISS_COARSE_MU_AVERAGE = 1 };
 
 /* A viscosity inclusion.  Sphere: a = (cx, cy, cz, r, -, -), region
@@ -175,6 +177,23 @@ typedef struct {
                            * at most a quarter, otherwise unpadded; a value
                            * 1..64 rounds q up to a multiple of it on every
                            * level. */
+    int coarse_solver;    /* ISS_COARSE_DIRECT (default): the bordered dense
+                           * inverse of the coarsest level, factored on the
+                           * host at first use.  ISS_COARSE_MINRES: the
+                           * Krylov coarse solver of Sec. 5 -- MINRES on the
+                           * coarsest level's system, block-diagonally
+                           * preconditioned by minres_cg Jacobi-preconditioned
+                           * CG steps on the velocity block and the lumped
+                           * (1/mu-weighted) pressure mass, minres_iters
+                           * steps from zero, with the constant pressure
+                           * removed from its right-hand side and the
+                           * weighted pressure mean from its result.  Sec. 5
+                           * pairs it with the strain form on the coarse grid
+                           * (coarse_form, coarse_rhs_mod): the CG needs a
+                           * positive definite velocity block. */
+    int minres_iters;     /* MINRES steps per coarse solve (default 30)     */
+    int minres_cg;        /* CG steps per preconditioner application
+                           * (default 5; 0: the Jacobi diagonal alone)      */
 } iss_options;
 
 typedef struct {

@@ -13,7 +13,8 @@ Readings taken where the paper is open:
     Q of Sec. 1);
   * the inner CG runs a fixed number of steps from zero, the outer MINRES a
     fixed number of steps from zero (the paper only asks that the stopping
-    criteria keep the multigrid rates);
+    criteria keep the multigrid rates); zero CG steps means the Jacobi
+    preconditioner of the velocity block alone;
   * the constant pressure, the null space of K, is removed from the
     right-hand side before the iteration (plain mean of the pressure
     residual) and the weighted pressure mean from the result, as the direct
@@ -107,7 +108,12 @@ class MinresCoarseSolver:
     def apply_Pinv(self, r):
         lv = self.lv
         out = np.empty_like(r)
-        out[:self.dN] = jacobi_pcg(lambda u: lv.A @ u, self.diagA, r[:self.dN], self.cg_iters)
+        if self.cg_iters > 0:
+            out[:self.dN] = jacobi_pcg(lambda u: lv.A @ u, self.diagA, r[:self.dN], self.cg_iters)
+        else:
+            # no CG step: the Jacobi preconditioner of the velocity block itself
+            d = self.diagA
+            out[:self.dN] = np.where(d > 0, r[:self.dN] / np.where(d > 0, d, 1.0), 0.0)
         out[self.dN:] = r[self.dN:] / lv.weights
         return out
 

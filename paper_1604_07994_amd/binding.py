@@ -38,9 +38,11 @@ class Options(ctypes.Structure):
                 ("coarse_mu", ctypes.c_int), ("coarse_form", ctypes.c_int), ("nu_inc", ctypes.c_int),
                 ("mid_form", ctypes.c_int), ("merge_max_n", ctypes.c_int), ("spec_wide_min", ctypes.c_int),
                 ("cycles", ctypes.c_int), ("f16_rms", ctypes.c_double), ("coarse_rhs_mod", ctypes.c_int),
-                ("bc", ctypes.c_int), ("split_align", ctypes.c_int)]
+                ("bc", ctypes.c_int), ("split_align", ctypes.c_int), ("coarse_solver", ctypes.c_int),
+                ("minres_iters", ctypes.c_int), ("minres_cg", ctypes.c_int)]
 
 BCS = {"noslip": 0, "freeslip": 1}
+COARSE_SOLVERS = {"direct": 0, "minres": 1}
 
 
 # iss_launch_kind: smoother kernel shapes counted by iss_launch_counts
@@ -178,13 +180,15 @@ class Problem:
     def __init__(self, dim, macro, levels, coarse, inclusions, mu, nu1=3, nu2=3, omega=0.3,
                  stab_beta=1.0 / 12.0, outer="richardson", restart=40, coarse_mu="average",
                  coarse_form=None, nu_inc=0, mid_form=None, merge_max_n=64, spec_wide_min=65536, cycles=1,
-                 f16_rms=1.0 / 1024.0, coarse_rhs_mod=False, elem_phase=None, bc="noslip", split_align=0):
+                 f16_rms=1.0 / 1024.0, coarse_rhs_mod=False, elem_phase=None, bc="noslip", split_align=0,
+                 coarse_solver="direct", minres_iters=30, minres_cg=5):
         L = lib()
         self.dim, self.macro, self.levels, self.coarse = dim, macro, levels, coarse
         opt = Options(nu1, nu2, omega, stab_beta, OUTER[outer], restart, COARSE_MU[coarse_mu],
                       -1 if coarse_form is None else FORMS[coarse_form], nu_inc,
                       -1 if mid_form is None else FORMS[mid_form], merge_max_n, spec_wide_min, cycles, f16_rms,
-                      int(bool(coarse_rhs_mod)), BCS[bc], split_align)
+                      int(bool(coarse_rhs_mod)), BCS[bc], split_align, COARSE_SOLVERS[coarse_solver],
+                      minres_iters, minres_cg)
         self.bc = bc
         mu_arr = (ctypes.c_double * len(mu))(*mu)
         h = ctypes.c_void_p()

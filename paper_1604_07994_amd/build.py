@@ -30,7 +30,8 @@ def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     jobs = []
-    for src, dev in (("iss_kernels.hip", True), ("iss_net.hip", True), ("iss_host.cpp", False)):
+    for src, dev in (("iss_kernels.hip", True), ("iss_net.hip", True), ("iss_krylov.hip", True),
+                     ("iss_host.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE_FLAGS
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

@@ -214,6 +214,13 @@ struct Coarse {
     double* d_Kinv_mod[3] = {nullptr, nullptr, nullptr};   // K^-1 T: right-hand side modified
     double* d_bc = nullptr;
     double* d_xc = nullptr;
+    // Krylov coarse solver (option coarse_solver = ISS_COARSE_MINRES)
+    bool kr_ready = false;
+    KrylovBufs kb{};
+    double* d_inv_diag[3] = {nullptr, nullptr, nullptr};   // per form
+    double* d_bb = nullptr;
+    double* d_xx = nullptr;
+    int32_t* d_all = nullptr;                               // 0 .. (d+1) N - 1
 };
 
 }  // namespace
@@ -851,6 +858,75 @@ int dense_inverse(std::vector<double>& A, int64_t M) {
     return ISS_OK;
 }
 
+// Preconditioner diagonals of the coarse Krylov solver for `form`: the
+// inverse diagonal of the velocity block A (0 on fixed dofs) and the
+// inverse lumped pressure mass 1 / w_j, w_j = sum_T |T| / ((d+1) mu_T).
+template <int D>
+void coarse_jacobi(const iss_problem* p, int form, std::vector<double>& inv_d) {
+    constexpr auto& K = Kuhn<D>::T;
+    constexpr int NT = KuhnTables<D>::NT;
+    const ElemTables<D, double>& E = *reinterpret_cast<const ElemTables<D, double>*>(
+        D == 3 ? (const void*)&p->t3 : (const void*)&p->t2);
+    const Level& L = p->lv[p->coarse];
+    const int n = L.v.n;
+    const int64_t n1 = n + 1, N = L.v.N;
+    std::vector<double> dg((size_t)(D + 1) * N, 0.0);
+    const int64_t ncell = (D == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+    double vol = 1.0;
+    for (int a = 0; a < D; ++a) vol /= n;
+    vol /= (D == 3 ? 6.0 : 2.0);
+    for (int64_t c = 0; c < ncell; ++c) {
+        const int ci = (int)(c % n), cj = (int)((c / n) % n), ck = (D == 3) ? (int)(c / ((int64_t)n * n)) : 0;
+        for (int ty = 0; ty < NT; ++ty) {
+            const int ph = L.elem_phase[c * NT + ty];
+            const double mu = L.mu_tab[ph], imu = L.imu_tab[ph];
+            for (int a = 0; a <= D; ++a) {
+                const int64_t v = (ci + K.type_vert[ty][a][0]) + n1 * (cj + K.type_vert[ty][a][1]) +
+                                  (D == 3 ? n1 * n1 * (ck + K.type_vert[ty][a][2]) : 0);
+                for (int l = 0; l < D; ++l)
+                    dg[(size_t)l * N + v] += mu * L.v.sA * E.Avis[form][ty][a * D + l][a * D + l];
+                dg[(size_t)D * N + v] += vol * imu / (D + 1);
+            }
+        }
+    }
+    inv_d.assign(dg.size(), 0.0);
+    for (int64_t v = 0; v < N; ++v) {
+        for (int l = 0; l < D; ++l)
+            if (!velocity_fixed(p, n, v, l)) inv_d[(size_t)l * N + v] = 1.0 / dg[(size_t)l * N + v];
+        inv_d[(size_t)D * N + v] = 1.0 / dg[(size_t)D * N + v];
+    }
+}
+
+int ensure_minres(iss_problem* p, int form) {
+    Coarse& cs = p->cs;
+    const Level& L = p->lv[p->coarse];
+    const int64_t n = (int64_t)(p->dim + 1) * L.v.N;
+    int rc;
+    if (!cs.kr_ready) {
+        const size_t bytes = (size_t)n * sizeof(double);
+        double** vecs[] = {&cs.kb.v[0], &cs.kb.v[1], &cs.kb.v[2], &cs.kb.z[0], &cs.kb.z[1], &cs.kb.w[0],
+                           &cs.kb.w[1], &cs.kb.w[2], &cs.kb.q, &cs.kb.t, &cs.kb.u, &cs.kb.r, &cs.kb.zc,
+                           &cs.kb.pc, &cs.kb.qc, &cs.d_bb, &cs.d_xx};
+        for (double** v : vecs) {
+            if ((rc = dev_alloc(p, (void**)v, bytes))) return rc;
+            ISS_HIP(hipMemset(*v, 0, bytes));
+        }
+        if ((rc = dev_alloc(p, (void**)&cs.kb.st, 16 * sizeof(double)))) return rc;
+        ISS_HIP(hipMemset(cs.kb.st, 0, 16 * sizeof(double)));
+        std::vector<int32_t> all((size_t)n);
+        for (int64_t i = 0; i < n; ++i) all[(size_t)i] = (int32_t)i;
+        if ((rc = dev_upload(p, &cs.d_all, all.data(), all.size()))) return rc;
+        cs.kr_ready = true;
+    }
+    if (!cs.d_inv_diag[form]) {
+        std::vector<double> inv_d;
+        if (p->dim == 3) coarse_jacobi<3>(p, form, inv_d);
+        else coarse_jacobi<2>(p, form, inv_d);
+        if ((rc = dev_upload(p, &cs.d_inv_diag[form], inv_d.data(), inv_d.size()))) return rc;
+    }
+    return ISS_OK;
+}
+
 // Inverse of the bordered coarse matrix of `form`; with mod, the inverse
 // times T = [[I, B^T M^-1], [0, I]], M the lumped (1/mu)-weighted pressure
 // mass (the weights of the pressure constraint): the coarse right-hand side
@@ -858,6 +934,7 @@ int dense_inverse(std::vector<double>& A, int64_t M) {
 // follows b(v, q) = -(div v, q)), which makes the strain-form coarse system
 // approximate the a_tr system of the finer levels where div u != 0.
 int ensure_coarse(iss_problem* p, int form, bool mod = false) {
+    if (p->opt.coarse_solver == ISS_COARSE_MINRES) return ensure_minres(p, form);
     Coarse& cs = p->cs;
     if (mod ? cs.d_Kinv_mod[form] : cs.d_Kinv[form]) return ISS_OK;
     std::vector<double> Kd;
@@ -950,6 +1027,15 @@ int coarse_solve(iss_problem* p, int form, int prec, const void* b, void* x, hip
         for (int f = 0; f <= p->dim; ++f) fm.m[f] = 1.0 / (f < p->dim ? p->sig_u : p->sig_p);
         fm.N = L.v.N;
         fm.on = 1;
+    }
+    if (p->opt.coarse_solver == ISS_COARSE_MINRES) {
+        const int64_t n = (int64_t)(p->dim + 1) * L.v.N;
+        KrylovBufs kb = cs.kb;
+        kb.inv_d = cs.d_inv_diag[form];
+        ISS_HIP(k_gather(prec, b, cs.d_all, n, cs.d_bb, s, fm));
+        ISS_HIP(minres_coarse(L.v, form, kb, p->opt.minres_iters, p->opt.minres_cg, mod, cs.d_bb, cs.d_xx, s));
+        ISS_HIP(k_scatter(prec, cs.d_xx, cs.d_all, n, x, s, fm));
+        return ISS_OK;
     }
     ISS_HIP(k_gather(prec, b, cs.d_free, m, cs.d_bc, s, fm));
     ISS_HIP(k_dense_matvec(mod ? cs.d_Kinv_mod[form] : cs.d_Kinv[form], cs.M, cs.d_bc, cs.d_xc, s));
@@ -1337,6 +1423,9 @@ int iss_default_options(iss_options* o) {
     o->coarse_rhs_mod = 0;
     o->bc = ISS_BC_NOSLIP;
     o->split_align = 0;
+    o->coarse_solver = ISS_COARSE_DIRECT;
+    o->minres_iters = 30;
+    o->minres_cg = 5;
     return ISS_OK;
 }
 
@@ -1435,7 +1524,9 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
         p->opt.merge_max_n < 0 || p->opt.spec_wide_min < 0 || p->opt.cycles < 1 || p->opt.cycles > 16 ||
         !(p->opt.f16_rms > 0) || !(p->opt.f16_rms < 65504.0) ||
         (p->opt.bc != ISS_BC_NOSLIP && p->opt.bc != ISS_BC_FREESLIP) || p->opt.split_align < 0 ||
-        p->opt.split_align > 64) {
+        p->opt.split_align > 64 ||
+        (p->opt.coarse_solver != ISS_COARSE_DIRECT && p->opt.coarse_solver != ISS_COARSE_MINRES) ||
+        p->opt.minres_iters < 1 || p->opt.minres_iters > 1000 || p->opt.minres_cg < 0 || p->opt.minres_cg > 100) {
         delete p;
         return fail(ISS_E_INVAL, "bad options");
     }

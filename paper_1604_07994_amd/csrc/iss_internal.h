@@ -134,6 +134,30 @@ hipError_t k_rhs_buoyancy(const LevelView& L, const uint8_t* buoyant_flag, doubl
 // b = (M f_1 | .. | M f_d | 0), fixed velocity entries zero; vol = |T|
 hipError_t k_rhs_nodal_force(const LevelView& L, const double* f, double vol, double* b, hipStream_t s);
 
+// ---- Krylov coarse solver (iss_krylov.hip)
+// device buffers of the coarse MINRES: (d+1) N doubles each on the coarsest
+// level, st 16 doubles of scalar state, inv_d the inverse Jacobi diagonal of
+// the velocity block (0 on fixed dofs) followed by 1 / w on the pressure
+struct KrylovBufs {
+    double* st;
+    const double* inv_d;
+    double* v[3];
+    double* z[2];
+    double* w[3];
+    double* q;
+    double* t;
+    double* u;
+    double* r;
+    double* zc;
+    double* pc;
+    double* qc;
+};
+// x = MINRES_{minres_iters}(K, P; b) from x = 0 on level L (form), P^-1 =
+// diag(CG_{cg_iters}(A, D_A), M_p^-1); with mod, b_u += B^T M_p^-1 b_p
+// first; b (overwritten: modified, projected) and x are FP64 vectors of L
+hipError_t minres_coarse(const LevelView& L, int form, const KrylovBufs& kb, int minres_iters, int cg_iters,
+                         bool mod, double* b, double* x, hipStream_t s);
+
 // ---- learned band correction (iss_net.hip)
 struct NetImpl;
 struct NetSetup {

@@ -115,3 +115,19 @@ def test_minres_coarse_solver_approaches_the_direct_solve():
     rd = rate()
     rm = rate(coarse_solver='minres', minres_iters=30, cg_iters=5)
     assert abs(rm - rd) < 0.02, (rm, rd)
+
+
+def test_zero_cg_steps_is_the_jacobi_block():
+    """With no CG step the velocity block of the preconditioner is the
+    Jacobi diagonal of A (and the pressure block the lumped mass)."""
+    w = iss_inputs.workload('columns_3d')
+    lv = mg.Level(3, 4, w['inclusions'], w['mu'], 'strain', bc='freeslip')
+    S = krylov.MinresCoarseSolver(lv, 5, 0)
+    r = np.random.default_rng(7).uniform(-1, 1, lv.K.shape[0]) * lv.free
+    out = S.apply_Pinv(r)
+    dN = 3 * lv.N
+    d = lv.A.diagonal()
+    free = lv.free[:dN]
+    assert np.allclose(out[:dN][free], r[:dN][free] / d[free], rtol=1e-15, atol=0)
+    assert np.all(out[:dN][~free] == 0)
+    assert np.allclose(out[dN:], r[dN:] / lv.weights, rtol=1e-15, atol=0)
