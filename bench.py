@@ -437,6 +437,24 @@ def main():
             phase, step = P.smooth_timed(form, xs, b, 5)
             smooth_ms[form] = {"velocity_colour_phase_ms": phase, "step_ms": step}
         log("apply GB/s: %s" % {k: round(v["GBs"], 1) for k, v in apply_gbs.items()})
+        # stabilised P1-P0 (Sec. 3) on the same lattice: K x with one pressure
+        # per element and the interior-penalty form, and the flux post-process
+        ne = P.num_elements()
+        xp = torch.rand(P.p1p0_size(), dtype=torch.float64, device=dev)
+        yp = torch.empty_like(xp)
+        fl = torch.empty(ne * (w["dim"] + 1), dtype=torch.float64, device=dev)
+        for form in ("interface", "strain"):
+            ms = event_time(lambda: P.p1p0_apply(form, xp, yp), 10)
+            # read u (3 fields), p (one per element), element and vertex
+            # phases; write K x: 3 * 8 + 8 ne / N + ne / N + 1 + 3 * 8 + 8 ne / N
+            bpv = 49 + 17 * ne / N
+            apply_gbs["p1p0/%s/full" % form] = {"ms": ms, "GBs": bpv * N / ms / 1e6, "bytes_per_vertex": bpv}
+        ms = event_time(lambda: P.p1p0_flux(xp, fl), 10)
+        bpv = 24 + 9 * ne / N + 4 * 8 * ne / N
+        apply_gbs["p1p0/flux"] = {"ms": ms, "GBs": bpv * N / ms / 1e6, "bytes_per_vertex": bpv}
+        del xp, yp, fl
+        log("P1-P0: %s" % {k: (round(v["ms"], 3), round(v["GBs"], 1)) for k, v in apply_gbs.items()
+                           if k.startswith("p1p0")})
         log("smoothing (HIP events): %s" % smooth_ms)
 
     # the paper's own configuration: a_tr (the call's form) on every level

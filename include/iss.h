@@ -285,6 +285,33 @@ int iss_rhs_buoyancy(iss_problem* p, int level, const int* phases, int nbuoyant,
 int iss_rhs_nodal_force(iss_problem* p, int level, const double* f, double* b,
                         iss_stream_t stream);
 
+/* Stabilised P1-P0 discretisation on the finest level (Sec. 3): P1
+ * velocity as above, one pressure per element, the interior-penalty
+ * stabilisation of eq. stabc,
+ *   c(p, q) = gamma sum_i 1/(2 mu_i) sum_{F interior to Omega_i}
+ *             |T1||T2| / (|T1| + |T2|) [p]_F [q]_F,
+ * (facets between elements of different viscosity and boundary facets are
+ * not penalised) and b(v, q) = -(div v, q).  A P1-P0 vector holds the d
+ * velocity fields of N entries followed by ne element pressures, element
+ * e = c * T + t in the order of iss_problem_create_elems (c the cell, t the
+ * type); fixed velocity entries as above.  iss_num_elements gives ne.
+ * The calls need ne >= N (every 3D lattice; 2D lattices with n >= 3);
+ * gamma > 0 (Sec. 4 takes gamma = 1).  Device FP64 vectors, caller-owned.
+ *
+ * iss_p1p0_apply: y = K x with K = [[A, B0^T], [B0, -C]], A the viscous
+ * form `form` as in iss_apply (the discrete problem of Sec. 3 takes a_tr,
+ * ISS_INTERFACE).
+ * iss_p1p0_flux: the post-processed facet fluxes of Sec. 3, flux[e (d+1)
+ * + a] = int_F u_h . n_T + gamma / (2 mu) |T||T'| / (|T| + |T'|)
+ * (p_T - p_T') for the facet F of element T = e opposite its local vertex a
+ * (local vertices in the order of the element's path through its cell,
+ * the second term only on penalised facets); the fluxes of an element sum
+ * to -(B0 u - C p)_T, zero for a solution of K x = (f, 0). */
+int iss_num_elements(const iss_problem* p, int64_t* ne);
+int iss_p1p0_apply(iss_problem* p, int form, double gamma, const double* x, double* y,
+                   iss_stream_t stream);
+int iss_p1p0_flux(iss_problem* p, double gamma, const double* x, double* flux, iss_stream_t stream);
+
 /* y = K x (block ISS_FULL_STOKES) or y = (A x_u, 0) (ISS_VELOCITY_ONLY) at
  * `level` with the viscous form `form`: the saddle-point operator of the
  * system of Sec. 5 with A from eq. standard (strain), eq. newbil applied

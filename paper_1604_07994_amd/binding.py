@@ -59,7 +59,8 @@ class SolveInfo(ctypes.Structure):
 
 
 EXPORTS = ["iss_default_options", "iss_problem_create", "iss_problem_destroy", "iss_num_vertices",
-           "iss_vertex_class", "iss_rhs_buoyancy", "iss_rhs_nodal_force", "iss_apply", "iss_residual", "iss_smooth",
+           "iss_vertex_class", "iss_rhs_buoyancy", "iss_rhs_nodal_force", "iss_num_elements", "iss_p1p0_apply",
+           "iss_p1p0_flux", "iss_apply", "iss_residual", "iss_smooth",
            "iss_restrict", "iss_prolong_add", "iss_coarse_solve", "iss_vcycle", "iss_solve",
            "iss_dot", "iss_last_error", "iss_net_create", "iss_net_destroy", "iss_net_info",
            "iss_net_band", "iss_net_set_weights", "iss_net_features", "iss_net_forward",
@@ -93,6 +94,9 @@ def lib():
     L.iss_vertex_class.argtypes = [vp, cint, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.iss_rhs_buoyancy.argtypes = [vp, cint, ctypes.POINTER(cint), cint, cdbl, vp, vp]
     L.iss_rhs_nodal_force.argtypes = [vp, cint, vp, vp, vp]
+    L.iss_num_elements.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.iss_p1p0_apply.argtypes = [vp, cint, cdbl, vp, vp, vp]
+    L.iss_p1p0_flux.argtypes = [vp, cdbl, vp, vp, vp]
     L.iss_apply.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
     L.iss_residual.argtypes = [vp, cint, cint, cint, vp, vp, vp, ctypes.POINTER(cdbl), vp]
     L.iss_smooth.argtypes = [vp, cint, cint, cint, cint, vp, vp, vp]
@@ -288,6 +292,33 @@ class Problem:
         _check(lib().iss_rhs_nodal_force(self._h, level, ctypes.c_void_p(f.data_ptr()),
                                          self._vec(b, level, torch.float64), _stream()))
         return b
+
+    # -- stabilised P1-P0 (finest level) ------------------------------------
+    def num_elements(self):
+        ne = ctypes.c_int64()
+        _check(lib().iss_num_elements(self._h, ctypes.byref(ne)))
+        return ne.value
+
+    def _p0vec(self, t, size):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype == torch.float64):
+            raise ValueError("expected a contiguous FP64 CUDA tensor")
+        if t.numel() != size:
+            raise ValueError("vector has %d entries, needs %d" % (t.numel(), size))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def p1p0_size(self):
+        return self.dim * self.num_vertices() + self.num_elements()
+
+    def p1p0_apply(self, form, x, y, gamma=1.0):
+        n = self.p1p0_size()
+        _check(lib().iss_p1p0_apply(self._h, FORMS[form], gamma, self._p0vec(x, n), self._p0vec(y, n), _stream()))
+        return y
+
+    def p1p0_flux(self, x, flux, gamma=1.0):
+        _check(lib().iss_p1p0_flux(self._h, gamma, self._p0vec(x, self.p1p0_size()),
+                                   self._p0vec(flux, (self.dim + 1) * self.num_elements()), _stream()))
+        return flux
 
     def apply(self, form, x, y, level=None, block="full"):
         level = self.levels if level is None else level

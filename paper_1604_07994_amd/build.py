@@ -31,7 +31,7 @@ def build(verbose=True):
     objs = []
     jobs = []
     for src, dev in (("iss_kernels.hip", True), ("iss_net.hip", True), ("iss_krylov.hip", True),
-                     ("iss_host.cpp", False)):
+                     ("iss_p1p0.hip", True), ("iss_host.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE_FLAGS
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

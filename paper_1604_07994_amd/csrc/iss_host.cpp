@@ -257,6 +257,7 @@ struct iss_problem {
     double* d_h = nullptr;          // m + 2 entries
     double* d_rate = nullptr;       // asymptotic-rate measurement: b = 0 and K x (2 vectors)
     uint8_t* d_flag = nullptr;      // 256 buoyancy flags
+    uint8_t* d_eph = nullptr;       // finest-level element phases (P1-P0 calls)
     double* h_pinned = nullptr;     // 8192 doubles of pinned host memory
     int64_t reorth_count = 0;       // second Gram-Schmidt passes (diagnostics)
     iss_net* net = nullptr;         // attached band correction (not owned)
@@ -1599,8 +1600,9 @@ static int create_impl(int dim, int macro, int levels, int coarse_level, const i
                 W.sC *= p->sig_p * p->sig_p;
             }
         }
-        // keep element phases only where the coarse matrix needs them
-        for (int l = coarse_level + 1; l <= levels; ++l) std::vector<uint8_t>().swap(p->lv[l].elem_phase);
+        // keep element phases where the coarse matrix and the P1-P0 calls
+        // (finest level) need them
+        for (int l = coarse_level + 1; l < levels; ++l) std::vector<uint8_t>().swap(p->lv[l].elem_phase);
     } while (0);
     if (rc) {
         iss_problem_destroy(p);
@@ -1664,6 +1666,43 @@ int iss_rhs_nodal_force(iss_problem* p, int level, const double* f, double* b, i
     for (int a = 0; a < p->dim; ++a) vol /= L.v.n;
     vol /= (p->dim == 3 ? 6.0 : 2.0);
     ISS_HIP(k_rhs_nodal_force(L.v, f, vol, b, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_num_elements(const iss_problem* p, int64_t* ne) {
+    if (!p || !ne) return fail(ISS_E_INVAL, "null argument");
+    const Level& L = p->lv[p->levels];
+    *ne = (int64_t)L.elem_phase.size();
+    return ISS_OK;
+}
+
+// the device copy of the finest level's element phases, and the argument
+// checks shared by the P1-P0 calls
+static int p1p0_prepare(iss_problem* p, double gamma) {
+    if (!(gamma > 0) || !std::isfinite(gamma)) return fail(ISS_E_INVAL, "gamma must be positive and finite");
+    const Level& L = p->lv[p->levels];
+    if ((int64_t)L.elem_phase.size() < L.v.N)
+        return fail(ISS_E_INVAL, "P1-P0 needs at least as many elements as vertices (3D, or 2D with n >= 3)");
+    if (!p->d_eph) {
+        int rc = dev_upload(p, &p->d_eph, L.elem_phase.data(), L.elem_phase.size());
+        if (rc) return rc;
+    }
+    return ISS_OK;
+}
+
+int iss_p1p0_apply(iss_problem* p, int form, double gamma, const double* x, double* y, iss_stream_t stream) {
+    if (!p || !x || !y) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = check_form(form)) || (rc = p1p0_prepare(p, gamma))) return rc;
+    ISS_HIP(k_p1p0_apply(p->lv[p->levels].v, form, p->d_eph, gamma, x, y, (hipStream_t)stream));
+    return ISS_OK;
+}
+
+int iss_p1p0_flux(iss_problem* p, double gamma, const double* x, double* flux, iss_stream_t stream) {
+    if (!p || !x || !flux) return fail(ISS_E_INVAL, "null argument");
+    int rc;
+    if ((rc = p1p0_prepare(p, gamma))) return rc;
+    ISS_HIP(k_p1p0_flux(p->lv[p->levels].v, p->d_eph, gamma, x, flux, (hipStream_t)stream));
     return ISS_OK;
 }
 

@@ -158,6 +158,14 @@ struct KrylovBufs {
 hipError_t minres_coarse(const LevelView& L, int form, const KrylovBufs& kb, int minres_iters, int cg_iters,
                          bool mod, double* b, double* x, hipStream_t s);
 
+// ---- stabilised P1-P0 (iss_p1p0.hip), finest level L; vectors hold the
+// d velocity fields of N vertices followed by one pressure per element
+// (cell * d! + type); eph: the element phases (device)
+hipError_t k_p1p0_apply(const LevelView& L, int form, const uint8_t* eph, double gamma, const double* x, double* y,
+                        hipStream_t s);
+hipError_t k_p1p0_flux(const LevelView& L, const uint8_t* eph, double gamma, const double* x, double* flux,
+                       hipStream_t s);
+
 // ---- learned band correction (iss_net.hip)
 struct NetImpl;
 struct NetSetup {
