@@ -151,3 +151,22 @@ def test_columns_solve_matches_direct(form):
     xh = problem.normalise_pressure(xh, d, n, lv.weights)
     assert _rel(xh, xs) < 1e-9, form
     P.close()
+
+
+@pytest.mark.parametrize("form", ["strain", "interface"])
+def test_smoother_step_fp32_freeslip(form):
+    """FP32 vectors and arithmetic on the free-slip columns problem, large
+    and merged kernels: one step within 1e-5 of max |x| of the FP64 oracle
+    run on the same FP32-rounded input (the tolerance of the no-slip FP32
+    tests)."""
+    import torch
+    for path in sorted(PATHS):
+        w = _workload("columns_3d", 2, 2)
+        P = gpu_problem(w, **PATHS[path])
+        lv = mg.Level(3, w["n"], w["inclusions"], w["mu"], form, bc="freeslip")
+        x = iss_inputs.random_vector(3, w["n"], seed=158, bc="freeslip").astype(np.float32).astype(np.float64)
+        b = iss_inputs.random_rhs(3, w["n"], seed=159, bc="freeslip").astype(np.float32).astype(np.float64)
+        xg = to_dev(x, torch.float32)
+        P.smooth(form, xg, to_dev(b, torch.float32), nsteps=1)
+        assert _rel(to_host(xg), mg.smooth(lv, x, b, 1)) < 1e-5, (form, path)
+        P.close()

@@ -88,3 +88,28 @@ def test_couette_fluxes_balance_on_the_gpu(level):
     scale = np.abs(B) @ np.abs(x[:3 * O.N])
     assert np.abs(yp).max() <= 1e-12 * scale.max()
     P.close()
+
+
+def test_p1p0_with_per_element_phases():
+    """A problem posed by one phase per element (random three-phase field):
+    the P1-P0 apply uses those element phases for the penalty facets."""
+    import torch
+    from paper_1604_07994_amd import Problem
+    from tests.test_gpu_boundary_api import library_elements
+    n, mu = 4, [1.0, 30.0, 900.0]
+    E = library_elements(3, n)
+    ph = np.random.default_rng(172).integers(0, 3, len(E)).astype(np.uint8)
+    P = Problem.from_elems(3, 2, 1, 1, ph, mu)
+    O = p1p0.P1P0(3, n, [], mu, mu_e=np.array(mu)[ph])
+    assert np.array_equal(mesh_elements_sorted(E), mesh_elements_sorted(O.E))
+    x = np.random.default_rng(173).uniform(-1, 1, O.ndof) * O.free_mask()
+    K = O.stokes("interface")
+    xg = to_dev(x)
+    y = torch.empty_like(xg)
+    P.p1p0_apply("interface", xg, y)
+    assert_close_scaled(to_host(y), K @ x, abs_scale(K, x), 1e-12, "P1-P0 apply, element phases")
+    P.close()
+
+
+def mesh_elements_sorted(E):
+    return np.sort(np.asarray(E), axis=1)
