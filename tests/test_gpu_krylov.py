@@ -130,3 +130,25 @@ def test_columns_rate_with_the_papers_coarse_grid(form):
     rd = Pd.asymptotic_rate(form, x0.clone(), iters=100)[-1]
     Pd.close()
     assert rm < 0.35 and rm < rd + 0.02, (form, rm, rd)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_minres_coarse_in_reduced_precision_vcycles(prec):
+    """The coarse Krylov solve gathers the coarse right-hand side into FP64
+    (undoing the field scaling of the FP16 cycle) and scatters back: an
+    FGMRES solve with an FP32 or FP16 V-cycle and the MINRES coarse grid
+    reaches 1e-8 on the 65^3 sphere (contrast 10^3) in at most twice the
+    FP64 iterations."""
+    import torch
+    w = small_workload("sphere_3d", 6)
+    kw = dict(outer="fgmres", restart=60, coarse_mu="average", coarse_form="strain", mid_form="strain",
+              nu1=3, nu2=3, nu_inc=2, omega=0.6, coarse_solver="minres")
+    P = gpu_problem(w, **kw)
+    b = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
+    P.rhs_buoyancy(b, w["buoyant"])
+    x = torch.zeros_like(b)
+    i64 = P.solve("interface", x, b, rtol=1e-8, maxit=200)
+    x.zero_()
+    ilo = P.solve("interface", x, b, prec=prec, rtol=1e-8, maxit=200)
+    assert ilo["relres"] <= 1e-8 and ilo["iterations"] <= 2 * i64["iterations"] + 2, (i64, ilo)
+    P.close()
