@@ -48,6 +48,8 @@ def test_argument_validation_without_gpu():
     assert opt.nu1 == 3 and opt.nu2 == 3 and abs(opt.omega - 0.3) < 1e-15
     assert opt.coarse_form == -1 and opt.mid_form == -1
     assert opt.merge_max_n == 64 and opt.spec_wide_min == 65536 and opt.cycles == 1
+    assert opt.bc == 0 and opt.split_align == 0 and opt.coarse_solver == 0
+    assert opt.minres_iters == 30 and opt.minres_cg == 5
 
 
 def _create(L, binding, dim=3, macro=1, levels=2, coarse=1, incs=(), mu=(1.0,), opt=None):
@@ -94,7 +96,9 @@ def test_problem_create_rejects_split_field_beyond_4gib():
                                          ("coarse_mu", 7), ("coarse_form", 3), ("stab_beta", 0.0),
                                          ("mid_form", -2), ("mid_form", 3), ("merge_max_n", -1),
                                          ("spec_wide_min", -1), ("cycles", 0), ("cycles", 17), ("f16_rms", 0.0),
-                                         ("f16_rms", 1e5)])
+                                         ("f16_rms", 1e5), ("bc", 2), ("split_align", -1), ("split_align", 65),
+                                         ("coarse_solver", 2), ("minres_iters", 0), ("minres_iters", 1001),
+                                         ("minres_cg", -1), ("minres_cg", 101)])
 def test_problem_create_rejects_bad_options(field, value):
     from paper_1604_07994_amd import binding
     L = binding.lib()
@@ -113,3 +117,7 @@ def test_null_arguments_are_rejected():
     assert L.iss_problem_create(3, 1, 2, 1, None, 0, mu, 1, None, None) == -1
     assert L.iss_apply(None, 2, 1, 2, 0, None, None, None) == -1
     assert L.iss_solve(None, 2, 0, 1e-8, 10, None, None, None, None) == -1
+    assert L.iss_rhs_nodal_force(None, 2, None, None, None) == -1
+    assert L.iss_num_elements(None, None) == -1
+    assert L.iss_p1p0_apply(None, 2, 1.0, None, None, None) == -1
+    assert L.iss_p1p0_flux(None, 1.0, None, None, None) == -1
