@@ -8,7 +8,7 @@ rho = 1 inside, no-slip walls.  Synthetic, seeded, generated on the device by
 the library (iss_rhs_buoyancy).  One "step" is one complete solve from x = 0
 to ||b - K x|| <= 1e-8 ||b|| with the interface (decoupled + a_tr interface
 rows) form in FP64: FGMRES(150) preconditioned by two stationary Uzawa
-V_var(4,4) cycles (two more smoothing steps per coarser level, omega 0.7,
+V_var(4,4) cycles (two more smoothing steps per coarser level, omega 0.8,
 element-averaged coarse viscosity, strain form on every level below the
 finest); the strain form is timed with the same solver.  The paper's own
 configuration (a_tr on every level but the coarsest) is run once for the
@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--workload", default="sinker_3d")
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--omega", type=float, default=0.7)
+    ap.add_argument("--omega", type=float, default=0.8)
     ap.add_argument("--nu", type=int, default=4, help="pre- and post-smoothing steps")
     ap.add_argument("--nu-inc", type=int, default=2,
                     help="variable V-cycle: extra smoothing steps per level below the finest")
