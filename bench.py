@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--quick", action="store_true", help="solves only, no apply/smoother timing")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time complete oracle solves of the 65^2 and 65^3 workloads (minutes of CPU)")
     ap.add_argument("--no-columns", action="store_true",
                     help="skip the viscosity-columns timing problem of the paper (257^3, free-slip)")
     return ap.parse_args()
@@ -124,6 +126,94 @@ print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'N': lv.N, 'relres': float(h
                       "coarse settings) on %s refined %d times (%d vertices): %d iterations in %.1f s on one "
                       "core, scaled by vertex count to %d vertices and to the GPU's %d iterations"
                       % (cycles, w["name"], lv_small, r["N"], r["its"], r["seconds"], N_full, its_gpu)}
+
+
+ORACLE_SOLVE = r"""
+import json, sys, time, numpy as np
+sys.path.insert(0, %r)
+import iss_inputs
+from oracle import multigrid as mg, problem as oprob
+w = iss_inputs.workload(%r)
+H = mg.Hierarchy(w['dim'], w['macro'], w['levels'], w['coarse'], w['inclusions'], w['mu'], %r,
+                 omega=%r, nu1=%d, nu2=%d, coarse_mu='average', coarse_form=%r, mid_form=%r, nu_inc=%d)
+lv = H.levels[w['levels']]
+if w['buoyant']:
+    b = oprob.rhs_buoyancy(w['dim'], w['n'], lv.disc.elems, lv.disc.phase_e, w['buoyant']) * lv.free
+else:
+    b = iss_inputs.random_rhs(w['dim'], w['n'], seed=%d)
+t = time.time()
+x, h = mg.solve_fgmres(H, b, rtol=1e-8, restart=%d, maxit=%d, cycles=%d)
+dt = time.time() - t
+print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'relres': float(h[-1])}))
+"""
+
+
+def full_solves(Problem, args, mid_form, coarse_form, forms, rhs_seed=177):
+    """Complete solves to 1e-8 of the two small workloads, measured on both
+    sides, nothing scaled: the GPU (median of 3 after one warm-up) and the
+    oracle on one host core per form (one run; setup and assembly
+    excluded).  The 65^2 split square (mu 10 / 1, seeded U[-1, 1] forcing)
+    with the plain multigrid of Sec. 5 (FGMRES(150) around one V(3,3)
+    cycle, omega 0.3, each form on every level); the 65^3 sphere (mu 1e3,
+    buoyancy) with the benchmark's solver."""
+    import torch
+    import iss_inputs
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    bench_cfg = dict(omega=args.omega, nu=args.nu, nu_inc=args.nu_inc, cycles=args.cycles, mid_form=mid_form,
+                     coarse_form=coarse_form)
+    plain_cfg = dict(omega=0.3, nu=3, nu_inc=0, cycles=1, mid_form=None, coarse_form=None)
+    out = {}
+    for name, label, cfg in (("square_split_2d", "square_split_2d 65^2 mu 10/1", plain_cfg),
+                             ("sphere_3d", "sphere_3d 65^3 mu 1e3", bench_cfg)):
+        procs = {}
+        for form in forms:          # the oracle runs in the background while the GPU solves
+            src = ORACLE_SOLVE % (ROOT, name, form, cfg["omega"], cfg["nu"], cfg["nu"], cfg["coarse_form"],
+                                  cfg["mid_form"], cfg["nu_inc"], rhs_seed, args.restart, args.maxit,
+                                  cfg["cycles"])
+            procs[form] = subprocess.Popen([sys.executable, "-c", src], stdout=subprocess.PIPE,
+                                           stderr=subprocess.PIPE, text=True, env=env)
+        w = iss_inputs.workload(name)
+        P = Problem.from_workload(w, outer="fgmres", restart=args.restart, coarse_mu="average", nu1=cfg["nu"],
+                                  nu2=cfg["nu"], nu_inc=cfg["nu_inc"], omega=cfg["omega"],
+                                  coarse_form=cfg["coarse_form"], mid_form=cfg["mid_form"], cycles=cfg["cycles"])
+        if w["buoyant"]:
+            b = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
+            P.rhs_buoyancy(b, w["buoyant"])
+        else:
+            b = torch.from_numpy(iss_inputs.random_rhs(w["dim"], w["n"], seed=rhs_seed)).cuda()
+        res = {}
+        for form in forms:
+            x = torch.zeros_like(b)
+            times = []
+            for rep in range(4):
+                x.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                info = P.solve(form, x, b, rtol=1e-8, maxit=args.maxit, raise_on_fail=False)
+                torch.cuda.synchronize()
+                if rep > 0:
+                    times.append(time.perf_counter() - t)
+            res[form] = {"gpu_seconds": sorted(times)[1], "gpu_iterations": info["iterations"],
+                         "gpu_relres": info["relres"]}
+        P.close()
+        for form, pr in procs.items():
+            so, se = pr.communicate(timeout=900)
+            if pr.returncode != 0:
+                raise RuntimeError(se[-2000:])
+            r = json.loads(so.strip().splitlines()[-1])
+            res[form].update({"oracle_seconds": r["seconds"], "oracle_iterations": r["its"],
+                              "oracle_relres": r["relres"],
+                              "oracle_over_gpu": r["seconds"] / res[form]["gpu_seconds"]})
+        out[label] = {"solver": "fgmres(%d), %d V(%d,%d) cycle(s) +%d per coarser level, omega %.2f, levels "
+                                "below the finest: %s, coarsest: %s" % (args.restart, cfg["cycles"], cfg["nu"],
+                                                                      cfg["nu"], cfg["nu_inc"], cfg["omega"],
+                                                                      cfg["mid_form"] or "same form",
+                                                                      cfg["coarse_form"] or "same form"),
+                      "forms": res}
+        log("full solves %s: %s" % (label, {f: (v["gpu_iterations"], v["oracle_iterations"],
+                                                 round(v["gpu_seconds"], 4), round(v["oracle_seconds"], 2))
+                                             for f, v in res.items()}))
+    return out
 
 
 def measured_traffic(kernel, form):
@@ -517,6 +607,11 @@ def main():
                                args.nu_inc, args.cycles, mid_form, coarse_form)
         except Exception as e:   # reported, never silently replaced
             cpu = {"error": str(e)[-300:]}
+        if args.cpu_full and "error" not in cpu:
+            try:
+                cpu["full_solves"] = full_solves(Problem, args, mid_form, coarse_form, forms)
+            except Exception as e:
+                cpu["full_solves"] = {"error": str(e)[-300:]}
     out = {
         "metric": "s to 1e-8 rel. residual & stencil GB/s: decoupled vs strain form, 1 MI355X",
         "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

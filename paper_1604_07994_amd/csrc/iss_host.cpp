@@ -635,6 +635,8 @@ int setup_level(iss_problem* p, int l) {
         }
     }
     for (int c = D + 1; c < 5; ++c) off[c] = (int64_t)spec.size();
+    int64_t mid[4] = {0, 0, 0, 0};
+    for (int c = 0; c <= D; ++c) mid[c] = off[c] + (int64_t)spec_by_col[c].size();
     if (l == p->levels) {
         L.h_vphase = vphase;
         L.h_spec = spec;
@@ -677,6 +679,7 @@ int setup_level(iss_problem* p, int l) {
     V.spec = L.d_spec;
     V.spec_eph = L.d_spec_eph;
     for (int c = 0; c < 5; ++c) V.spec_off[c] = off[c];
+    for (int c = 0; c < 4; ++c) V.spec_mid[c] = mid[c];
     V.mu64 = L.d_mu64;
     V.imu64 = L.d_imu64;
     V.mu32 = L.d_mu32;

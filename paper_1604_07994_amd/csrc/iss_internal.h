@@ -30,6 +30,7 @@ struct LevelView {
     const int32_t* spec;     // special vertices grouped by colour
     const uint8_t* spec_eph; // per special vertex: phase of each slot
     int64_t spec_off[5];     // colour c occupies [spec_off[c], spec_off[c+1])
+    int64_t spec_mid[4];     // colour c: boundary rows before spec_mid[c], interior ones after
     const double* mu64;      // viscosity per phase
     const double* imu64;     // 1 / viscosity per phase
     const float* mu32;

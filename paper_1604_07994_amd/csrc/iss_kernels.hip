@@ -71,14 +71,23 @@ template <> struct PrecU<float> {
 // ----------------------------------------------------------------------------
 // thread -> vertex maps
 
-// Spread consecutive workgroups over the 8 XCDs in contiguous chunks: the
-// dispatcher sends workgroup b to XCD b % 8, so remapping makes every XCD
-// walk one contiguous range of the linear work order (used by the 1D
-// vector kernels).
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
-    const int64_t x = b & 7, idx = b >> 3;
-    const int64_t per = nb >> 3, rem = nb & 7;
-    return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+// Hand the 8 XCDs runs of g consecutive work blocks in turn (used by the
+// special-row kernels, whose lists run plane by plane).  The dispatcher
+// sends workgroup b to XCD b % 8, so within each stretch of 8 g workgroups
+// XCD x takes the blocks [x g, (x + 1) g) of the stretch: rows of
+// neighbouring z-planes, a few blocks apart in a list, share most of their
+// neighbour lines and now meet in one L2, while every XCD still takes its
+// share of every part of the list (boundary rows first, then the more
+// costly interior ones).  g = nb / 32 within [2, 16]: 16 on the large
+// levels, a few on small grids.  A last stretch shorter than 8 g keeps the
+// identity map; the map is a permutation of [0, nb).
+__device__ __forceinline__ int64_t xcd_group_remap(int64_t b, int64_t nb) {
+    const int64_t g = nb < 64 ? 2 : (nb >= 512 ? 16 : nb >> 5);
+    const int64_t span = 8 * g;
+    const int64_t st = b / span;
+    if ((st + 1) * span > nb) return b;
+    const int64_t r = b - st * span;
+    return st * span + (r & 7) * g + (r >> 3);
 }
 
 // Stencil kernels split the interior rows j = 1..m into 8 slabs of
@@ -479,7 +488,7 @@ __global__ __launch_bounds__(256) void k_apply_bulk(LevelView L, const T* __rest
 template <int D, int F, int BLK, int MODE, typename T>
 __global__ __launch_bounds__(256) void k_apply_special(LevelView L, const T* __restrict__ x,
                                                        const T* __restrict__ b, T* __restrict__ y) {
-    apply_special_body<D, F, BLK, MODE, T>(L, (int64_t)blockIdx.x * 256 + threadIdx.x, x, b, y);
+    apply_special_body<D, F, BLK, MODE, T>(L, xcd_group_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x, x, b, y);
 }
 
 // ----------------------------------------------------------------------------
@@ -1351,12 +1360,13 @@ __device__ __forceinline__ void gs_p_special_body(const LevelView& L, int colour
 // costs more than the lower occupancy of the merged one.  The merged grid is
 // made of one-wave workgroups: four per 256-thread bulk group first, then
 // the special rows.
-// The velocity special-only kernel uses one-wave workgroups: its lists start
-// with boundary vertices, which exit at once (Dirichlet), so with one wave
-// per workgroup the scattered interface rows spread over every CU instead of
-// the last few hundred 4-wave groups.  In the pressure kernel every row does
-// work; long lists keep 4-wave groups (neighbouring boundary rows share a
-// CU's L1), short ones use one wave per group to reach more CUs.
+// The velocity special-only kernel uses one-wave workgroups, so the
+// scattered interface rows spread over every CU; under no-slip it starts at
+// the first interior row of the colour (the boundary rows before it are
+// fixed).  In the pressure kernel every row does work; long lists keep
+// 4-wave groups (neighbouring boundary rows share a CU's L1), short ones use
+// one wave per group to reach more CUs.  The special-only kernels hand the
+// XCDs runs of consecutive blocks of their list (xcd_group_remap).
 constexpr int SPEC_WG = 64;
 template <int D, int F, bool BWD, typename T>
 __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __restrict__ xs,
@@ -1367,7 +1377,9 @@ __global__ __launch_bounds__(256) void k_gs_vel_s(LevelView L, int colour, T* __
 template <int D, int F, bool BWD, typename T>
 __global__ __launch_bounds__(SPEC_WG) void k_gs_vel_special_s(LevelView L, int colour, T* __restrict__ xs,
                                                               const T* __restrict__ bs) {
-    gs_vel_special_body<D, F, BWD, T>(L, colour, (int64_t)blockIdx.x * SPEC_WG + threadIdx.x, xs, bs);
+    const int64_t skip = L.freeslip ? 0 : L.spec_mid[colour] - L.spec_off[colour];
+    gs_vel_special_body<D, F, BWD, T>(L, colour, skip + xcd_group_remap(blockIdx.x, gridDim.x) * SPEC_WG + threadIdx.x,
+                                      xs, bs);
 }
 
 template <int D, int F, bool BWD, typename T>
@@ -1388,7 +1400,7 @@ __global__ __launch_bounds__(256) void k_gs_p_s(LevelView L, int colour, const T
 template <int D, typename T, int WG>
 __global__ __launch_bounds__(WG) void k_gs_p_special_s(LevelView L, int colour, const T* __restrict__ xs,
                                                        const T* __restrict__ bs, T* __restrict__ delta) {
-    gs_p_special_body<D, T>(L, colour, (int64_t)blockIdx.x * WG + threadIdx.x, xs, bs, delta);
+    gs_p_special_body<D, T>(L, colour, xcd_group_remap(blockIdx.x, gridDim.x) * WG + threadIdx.x, xs, bs, delta);
 }
 
 template <int D, typename T>
@@ -2039,6 +2051,9 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
             const int c = pass == 0 ? cc : D - cc;
             const int64_t ns = special_blocks(L.spec_off[c + 1] - L.spec_off[c]);
             const int64_t nsw = special_blocks(L.spec_off[c + 1] - L.spec_off[c], SPEC_WG);
+            // the special-only launch covers the interior rows alone under no-slip
+            const int64_t nsv = special_blocks(L.spec_off[c + 1] - (L.freeslip ? L.spec_off[c] : L.spec_mid[c]),
+                                               SPEC_WG);
             const int tq = tm ? tm->used++ : 0;
             if (tm) (void)hipEventRecord(tm->begin[tq], s);
             if (merge && bc > 0 && ns > 0) {
@@ -2059,12 +2074,12 @@ static hipError_t smooth_t(const LevelView& L, double omega, T* xs, const T* bs,
                     counted(L, ISS_L_GS_VEL_BULK);
                 }
                 if (tm) (void)hipEventRecord(tm->end[tq], s);
-                if (ns > 0) {
+                if (nsv > 0) {
                     if (pass == 0)
-                        hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L,
+                        hipLaunchKernelGGL((k_gs_vel_special_s<D, F, false, T>), dim3((unsigned)nsv), dim3(SPEC_WG), 0, s, L,
                                            c, xs, bs);
                     else
-                        hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)nsw), dim3(SPEC_WG), 0, s, L,
+                        hipLaunchKernelGGL((k_gs_vel_special_s<D, F, true, T>), dim3((unsigned)nsv), dim3(SPEC_WG), 0, s, L,
                                            c, xs, bs);
                     counted(L, ISS_L_GS_VEL_SPECIAL);
                 }

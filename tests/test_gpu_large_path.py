@@ -53,16 +53,29 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def _check_large_launches(c, d, path, steps, form):
+def _interior_special_colours(P, d, n):
+    """Colours (i + j + k mod d + 1) that hold an interior interface vertex:
+    under no-slip the velocity special launch of a colour covers only those
+    rows (the boundary ones are fixed), and is made only if there are any."""
+    cls = P.vertex_class()[0].reshape((n + 1,) * d)
+    col = sum(np.indices(cls.shape)) % (d + 1)
+    inner = ((cls & 1) != 0) & ((cls & 2) == 0)
+    return {c for c in range(d + 1) if inner[col == c].any()}
+
+
+def _check_large_launches(c, d, path, steps, form, colours):
     """Launch counts of `steps` smoothing steps on one level through the
     large-level kernels (every colour list holds boundary vertices, so every
-    special launch is made; the gradient and interface forms skip the
+    pressure special launch is made; velocity special launches are made for
+    the colours in `colours`; the gradient and interface forms skip the
     repeated colour at the turn of the symmetric sweep)."""
     m = d + 1
-    vel = (2 * m if form == "strain" else 2 * m - 1) * steps
+    seq = list(range(m)) + list(range(m - 1 if form == "strain" else m - 2, -1, -1))
+    vel = len(seq) * steps
     assert c["gs_vel_merged"] == c["p_rhs_merged"] == c["gs_p_merged"] == 0, c
     assert c["vel_rhs"] == steps and c["p_rhs_grouped"] == steps, c
-    assert c["gs_vel_bulk"] == vel and c["gs_vel_special"] == vel, c
+    assert c["gs_vel_bulk"] == vel, c
+    assert c["gs_vel_special"] == sum(k in colours for k in seq) * steps, (c, colours)
     assert c["gs_p_bulk"] == d * steps, c
     if path == "large-wide":
         assert c["gs_p_special_wide"] == m * steps and c["gs_p_special"] == 0, c
@@ -113,7 +126,8 @@ def test_smoother_steps_large_path(case, form):
     xg = to_dev(x)
     P.launch_counts(reset=True)
     P.smooth(form, xg, to_dev(b), nsteps=2)
-    _check_large_launches(P.launch_counts(), w["dim"], path, 2, form)
+    _check_large_launches(P.launch_counts(), w["dim"], path, 2, form,
+                          _interior_special_colours(P, w["dim"], w["n"]))
     ref = mg.smooth(lv, x, b, 2)
     assert _rel(to_host(xg), ref) < 1e-11, form
 
@@ -128,7 +142,8 @@ def test_smoother_step_fp32_large_path(case, form):
     xg = to_dev(x, torch.float32)
     P.launch_counts(reset=True)
     P.smooth(form, xg, to_dev(b, torch.float32), nsteps=1)
-    _check_large_launches(P.launch_counts(), w["dim"], path, 1, form)
+    _check_large_launches(P.launch_counts(), w["dim"], path, 1, form,
+                          _interior_special_colours(P, w["dim"], w["n"]))
     ref = mg.smooth(lv, x, b, 1)
     assert _rel(to_host(xg), ref) < 1e-5, form
 
