@@ -883,17 +883,18 @@ __global__ __launch_bounds__(256) void k_p_rhs_g(LevelView L, const T* __restric
 }
 
 // ----------------------------------------------------------------------------
-// LDS-tiled z-marching right-hand-side passes of the levels above 65^3 (3D).
+// LDS-tiled z-marching passes of the levels above 65^3 (3D): the right-hand
+// sides of the smoother and the operator applies.
 //
 // A workgroup owns a tile of ZT_X canonical x positions by ZT_Y rows and a
-// chunk of ZT_Z planes of the interior.  The planes k-1, k, k+1 of every
-// field its stencils read sit in LDS (a ring of three plane slots holding
-// the tile and a one-vertex ring around it), so every value comes from
-// memory once per tile instead of once per stencil entry, with full-width
-// loads.  The loads of plane k+2 are issued before plane k is computed and
-// stored to the freed slot after it.  Workgroup b runs on XCD b % 8; each
-// XCD walks a slab of tile rows (x tiles fastest, then rows, then z
-// chunks), so the tiles whose rings overlap share its L2.
+// chunk of zc planes of the interior.  One plane of every field its
+// stencils read (the tile and a one-vertex ring around it) sits in LDS at a
+// time, so every value comes from memory once per tile instead of once per
+// stencil entry, with full-width loads; the loads of the next plane are
+// issued before the current one is used and stored to the second slot
+// after it.  Workgroup b runs on XCD b % 8; each XCD walks a slab of tile
+// rows (x tiles fastest, then rows, then z chunks), so the tiles whose
+// rings overlap share its L2.
 constexpr int ZT_X = 64, ZT_Y = 4;
 constexpr int ZT_W = ZT_X + 2, ZT_H = ZT_Y + 2, ZT_A = ZT_W * ZT_H;
 constexpr int ZT_PER = (ZT_A + 255) / 256;   // loads per thread per field plane
@@ -965,8 +966,8 @@ __device__ __forceinline__ void ztile_fetch(const LevelView& L, const T* __restr
     }
 }
 
-template <int NF, typename C>
-__device__ __forceinline__ void ztile_store(C (*lds)[3][ZT_A], int slot, const C (&reg)[NF][ZT_PER]) {
+template <int NF, int NS, typename C>
+__device__ __forceinline__ void ztile_store(C (*lds)[NS][ZT_A], int slot, const C (&reg)[NF][ZT_PER]) {
 #pragma unroll
     for (int q = 0; q < ZT_PER; ++q) {
         const int e = (int)threadIdx.x + 256 * q;
@@ -977,114 +978,128 @@ __device__ __forceinline__ void ztile_store(C (*lds)[3][ZT_A], int slot, const C
     }
 }
 
-// The z march shared by the tiled passes: fills the ring of plane slots and
-// calls body(i, j, k, slot of k-1, slot of k, slot of k+1, active) for
-// every plane of the chunk (every thread of the workgroup takes part; the
-// body writes only if active).
+// The streaming form of the z march, for passes whose rows are sums of
+// weighted values: a thread reads only plane kk of the tile (its own
+// position and the in-plane neighbours the stencil reaches) and adds each
+// value into every row that reads it, row (i, j, kk - dz) for the offsets
+// (dx, dy, dz) that land on it; the rows kk - 1, kk and kk + 1 are rolling
+// sums in registers, and row kk - 1 is complete once plane kk is in.  Half
+// the LDS reads of the three-plane ring, and two plane slots instead of
+// three.  body(i, j, kk, slot of kk, emit): emit is set for active threads
+// whose row kk - 1 lies in the chunk.
 template <int NF, bool SPLIT, typename T, typename C, typename Body>
-__device__ __forceinline__ void ztile_march(const LevelView& L, ZTileGrid zg, const T* __restrict__ xs, int f0,
-                                            C (*lds)[3][ZT_A], Body&& body) {
+__device__ __forceinline__ void ztile_stream(const LevelView& L, ZTileGrid zg, const T* __restrict__ xs, int f0,
+                                             C (*lds)[2][ZT_A], Body&& body) {
     int i0, j0, k0, k1;
     if (!ztile_origin(L, zg, i0, j0, k0, k1)) return;
     const int tx = (int)threadIdx.x & (ZT_X - 1), ty = (int)threadIdx.x / ZT_X;
     const int i = i0 + tx, j = j0 + ty;
     const bool active = i <= L.n - 1 && j <= L.n - 1;
     C reg[NF][ZT_PER];
-    for (int p = 0; p < 3; ++p) {
-        ztile_fetch<NF, SPLIT, T, C>(L, xs, f0, i0, j0, k0 - 1 + p, reg);
-        ztile_store<NF, C>(lds, p, reg);
-    }
+    ztile_fetch<NF, SPLIT, T, C>(L, xs, f0, i0, j0, k0 - 1, reg);
+    ztile_store<NF, 2, C>(lds, 0, reg);
     __syncthreads();
-    int sm = 0, s0 = 1, sp = 2;
-    for (int k = k0; k < k1; ++k) {
-        const bool pre = k + 1 < k1;
-        if (pre) ztile_fetch<NF, SPLIT, T, C>(L, xs, f0, i0, j0, k + 2, reg);
-        body(i, j, k, sm, s0, sp, active);
+    int cur = 0;
+    for (int kk = k0 - 1; kk <= k1; ++kk) {
+        // the slot written here was last read before the previous barrier
+        const bool pre = kk < k1;
+        if (pre) ztile_fetch<NF, SPLIT, T, C>(L, xs, f0, i0, j0, kk + 1, reg);
+        body(i, j, kk, cur, active && kk - 1 >= k0);
+        if (pre) ztile_store<NF, 2, C>(lds, cur ^ 1, reg);
         __syncthreads();
-        if (pre) ztile_store<NF, C>(lds, sm, reg);
-        __syncthreads();
-        const int t = sm;
-        sm = s0;
-        s0 = sp;
-        sp = t;
+        cur ^= 1;
     }
 }
 
 // s = B u - C p - g on interior isoviscous vertices, colour 0 finishing its
 // first pressure Gauss-Seidel phase (delta = s / C_vv), as k_p_rhs_g.
+// Streamed: dv[r], cp[r] hold the divergence and stabilisation sums of the
+// rows kk - 1 (r = 0), kk (1) and kk + 1 (2).
 template <typename T>
 __global__ __launch_bounds__(256) void k_p_rhs_z(LevelView L, ZTileGrid zg, const T* __restrict__ xs,
                                                  const T* __restrict__ bs, T* __restrict__ sres, T* __restrict__ delta) {
     using C = typename Acc<T>::type;
     constexpr int D = 3;
-    __shared__ C lds[D + 1][3][ZT_A];
+    __shared__ C lds[D + 1][2][ZT_A];
     const C sdv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
     const C vol = (C)kuhn_volume<D>();
     constexpr int c0 = sc_int<D>(0);
-    ztile_march<D + 1, true, T, C>(L, zg, xs, 0, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+    C dv[3] = {0, 0, 0}, cp[3] = {0, 0, 0};
+    ztile_stream<D + 1, true, T, C>(L, zg, xs, 0, lds, [&](int i, int j, int kk, int slot, bool emit) {
         const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
-        C dv = 0, cp = 0;
         static_for<0, KuhnTables<D>::NB>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
             constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
-            const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+            constexpr int r = 1 - dz;          // the value at plane kk belongs to row kk - dz
             const int e = cen + dy * ZT_W + dx;
             static_for<0, D>([&](auto fc) {
                 constexpr int f = decltype(fc)::value;
                 constexpr int w = sdiv_int<D>(f, o);
-                if constexpr (w != 0) dv += (C)w * lds[f][slot][e];
+                if constexpr (w != 0) dv[r] += (C)w * lds[f][slot][e];
             });
             constexpr int wc = sc_int<D>(o);
-            if constexpr (wc != 0) cp += (C)wc * lds[D][slot][e];
+            if constexpr (wc != 0) cp[r] += (C)wc * lds[D][slot][e];
         });
-        if (!active) return;
-        const uint32_t v = sidx3(L, i, j, k);
-        const int ph = L.vphase_s[v];
-        if (ph == SPECIAL) return;
-        const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
-        const C sv = sdv * dv - sci * (vol * cp) - (C)ld32(bs + (int64_t)D * L.Ns, v);
-        if (((i + j + k) & 3) == 0) delta[v] = (T)(sv / (sci * (vol * (C)c0)));
-        else sres[v] = (T)sv;
+        if (emit) {
+            const int k = kk - 1;
+            const uint32_t v = sidx3(L, i, j, k);
+            const int ph = L.vphase_s[v];
+            if (ph != SPECIAL) {
+                const C sci = (C)L.sC * PrecU<C>::imu(L, ph);
+                const C sv = sdv * dv[0] - sci * (vol * cp[0]) - (C)ld32(bs + (int64_t)D * L.Ns, v);
+                if (((i + j + k) & 3) == 0) delta[v] = (T)(sv / (sci * (vol * (C)c0)));
+                else sres[v] = (T)sv;
+            }
+        }
+        dv[0] = dv[1]; dv[1] = dv[2]; dv[2] = 0;
+        cp[0] = cp[1]; cp[1] = cp[2]; cp[2] = 0;
     });
 }
 
-// g = f - B^T p on interior isoviscous vertices, as k_vel_rhs_s.
+// g = f - B^T p on interior isoviscous vertices, as k_vel_rhs_s; acc[r]
+// holds the streamed sums of the rows kk - 1, kk and kk + 1.
 template <typename T>
 __global__ __launch_bounds__(256) void k_vel_rhs_z(LevelView L, ZTileGrid zg, const T* __restrict__ xs,
                                                    const T* __restrict__ bs, T* __restrict__ g) {
     using C = typename Acc<T>::type;
     constexpr int D = 3;
-    __shared__ C lds[1][3][ZT_A];
+    __shared__ C lds[1][2][ZT_A];
     const C sbv = (C)(L.sB * (-kuhn_volume<D>() / (D + 1)));
-    ztile_march<1, true, T, C>(L, zg, xs, D, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+    C acc[3][D] = {};
+    ztile_stream<1, true, T, C>(L, zg, xs, D, lds, [&](int i, int j, int kk, int slot, bool emit) {
         const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
-        C acc[D] = {0, 0, 0};
         static_for<0, KuhnTables<D>::NB>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
             constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
+            constexpr int r = 1 - dz;          // the value at plane kk belongs to row kk - dz
             constexpr bool used = sbt_int<D>(0, o) != 0 || sbt_int<D>(1, o) != 0 || sbt_int<D>(2, o) != 0;
             if constexpr (used) {
-                const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
                 const C pv = lds[0][slot][cen + dy * ZT_W + dx];
                 static_for<0, D>([&](auto lc) {
                     constexpr int l = decltype(lc)::value;
                     constexpr int w = sbt_int<D>(l, o);
-                    if constexpr (w != 0) acc[l] += (C)w * pv;
+                    if constexpr (w != 0) acc[r][l] += (C)w * pv;
                 });
             }
         });
-        if (!active) return;
-        const uint32_t v = sidx3(L, i, j, k);
-        if (L.vphase_s[v] == SPECIAL) return;
+        if (emit) {
+            const uint32_t v = sidx3(L, i, j, kk - 1);
+            if (L.vphase_s[v] != SPECIAL) {
 #pragma unroll
-        for (int l = 0; l < D; ++l)
-            g[(int64_t)l * L.Ns + v] = (T)((C)ld32(bs + (int64_t)l * L.Ns, v) - sbv * acc[l]);
+                for (int l = 0; l < D; ++l)
+                    g[(int64_t)l * L.Ns + v] = (T)((C)ld32(bs + (int64_t)l * L.Ns, v) - sbv * acc[0][l]);
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            acc[0][l] = acc[1][l]; acc[1][l] = acc[2][l]; acc[2][l] = 0;
+        }
     });
 }
 
 // Operator apply / residual on the interior isoviscous vertices of a large
-// 3D level (canonical layout), as apply_bulk_body: the LDS z march with the
-// compile-time integer stencils of the Kuhn lattice (viscous block times
+// 3D level (canonical layout), as apply_bulk_body: the streamed LDS z march
+// with the compile-time integer stencils of the Kuhn lattice (viscous block times
 // |T|, B and B^T times -|T|/(d+1), C times |T|).
 template <int F, int BLK, int MODE, typename T>
 __global__ __launch_bounds__(256) void k_apply_z(LevelView L, ZTileGrid zg, const T* __restrict__ x,
@@ -1092,31 +1107,32 @@ __global__ __launch_bounds__(256) void k_apply_z(LevelView L, ZTileGrid zg, cons
     using C = typename Acc<T>::type;
     constexpr int D = 3;
     constexpr int NF = (BLK == BLOCK_FULL) ? D + 1 : D;
-    __shared__ C lds[NF][3][ZT_A];
+    __shared__ C lds[NF][2][ZT_A];
     const C vol = (C)kuhn_volume<D>();
     const C bvol = (C)(-kuhn_volume<D>() / (D + 1));
-    ztile_march<NF, false, T, C>(L, zg, x, 0, lds, [&](int i, int j, int k, int sm, int s0, int sp, bool active) {
+    // streamed sums of the rows kk - 1 (index 0), kk (1) and kk + 1 (2)
+    C av[3][D] = {}, bt[3][D] = {}, dv[3] = {0, 0, 0}, cp[3] = {0, 0, 0};
+    ztile_stream<NF, false, T, C>(L, zg, x, 0, lds, [&](int i, int j, int kk, int slot, bool emit) {
         const int cen = (1 + (int)threadIdx.x / ZT_X) * ZT_W + 1 + ((int)threadIdx.x & (ZT_X - 1));
-        C av[D] = {0, 0, 0}, bt[D] = {0, 0, 0}, dv = 0, cp = 0;
         static_for<0, KuhnTables<D>::NB>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
             constexpr int dx = Kuhn<D>::T.off[o][0], dy = Kuhn<D>::T.off[o][1], dz = Kuhn<D>::T.off[o][2];
-            const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+            constexpr int r = 1 - dz;          // the value at plane kk belongs to row kk - dz
             const int e = cen + dy * ZT_W + dx;
             static_for<0, D>([&](auto kc) {
-                constexpr int kk = decltype(kc)::value;
-                constexpr bool used = svis_int<D>(F, 0, kk, o) != 0 || svis_int<D>(F, 1, kk, o) != 0 ||
-                                      svis_int<D>(F, 2, kk, o) != 0 || (BLK == BLOCK_FULL && sdiv_int<D>(kk, o) != 0);
+                constexpr int kf = decltype(kc)::value;
+                constexpr bool used = svis_int<D>(F, 0, kf, o) != 0 || svis_int<D>(F, 1, kf, o) != 0 ||
+                                      svis_int<D>(F, 2, kf, o) != 0 || (BLK == BLOCK_FULL && sdiv_int<D>(kf, o) != 0);
                 if constexpr (used) {
-                    const C u = lds[kk][slot][e];
+                    const C u = lds[kf][slot][e];
                     static_for<0, D>([&](auto lc) {
                         constexpr int l = decltype(lc)::value;
-                        constexpr int wv = svis_int<D>(F, l, kk, o);
-                        if constexpr (wv != 0) av[l] += (C)wv * u;
+                        constexpr int wv = svis_int<D>(F, l, kf, o);
+                        if constexpr (wv != 0) av[r][l] += (C)wv * u;
                     });
                     if constexpr (BLK == BLOCK_FULL) {
-                        constexpr int wd = sdiv_int<D>(kk, o);
-                        if constexpr (wd != 0) dv += (C)wd * u;
+                        constexpr int wd = sdiv_int<D>(kf, o);
+                        if constexpr (wd != 0) dv[r] += (C)wd * u;
                     }
                 }
             });
@@ -1128,31 +1144,41 @@ __global__ __launch_bounds__(256) void k_apply_z(LevelView L, ZTileGrid zg, cons
                     static_for<0, D>([&](auto lc) {
                         constexpr int l = decltype(lc)::value;
                         constexpr int wb = sbt_int<D>(l, o);
-                        if constexpr (wb != 0) bt[l] += (C)wb * pv;
+                        if constexpr (wb != 0) bt[r][l] += (C)wb * pv;
                     });
                     constexpr int wc = sc_int<D>(o);
-                    if constexpr (wc != 0) cp += (C)wc * pv;
+                    if constexpr (wc != 0) cp[r] += (C)wc * pv;
                 }
             }
         });
-        if (!active) return;
-        const int64_t v = (int64_t)i + (int64_t)j * L.sy + (int64_t)k * L.sz;
-        const int ph = L.vphase[v];
-        if (ph == SPECIAL) return;
-        const C smu = PrecU<C>::mu(L, ph) * (C)L.sA * vol;
-        const C sb = (C)L.sB * bvol;
-        C out[D + 1];
+        if (emit) {
+            const int k = kk - 1;
+            const int64_t v = (int64_t)i + (int64_t)j * L.sy + (int64_t)k * L.sz;
+            const int ph = L.vphase[v];
+            if (ph != SPECIAL) {
+                const C smu = PrecU<C>::mu(L, ph) * (C)L.sA * vol;
+                const C sb = (C)L.sB * bvol;
+                C out[D + 1];
 #pragma unroll
-        for (int l = 0; l < D; ++l) out[l] = smu * av[l] + (BLK == BLOCK_FULL ? sb * bt[l] : (C)0);
-        out[D] = (BLK == BLOCK_FULL) ? sb * dv - (C)L.sC * PrecU<C>::imu(L, ph) * (vol * cp) : (C)0;
+                for (int l = 0; l < D; ++l) out[l] = smu * av[0][l] + (BLK == BLOCK_FULL ? sb * bt[0][l] : (C)0);
+                out[D] = (BLK == BLOCK_FULL) ? sb * dv[0] - (C)L.sC * PrecU<C>::imu(L, ph) * (vol * cp[0]) : (C)0;
 #pragma unroll
-        for (int f = 0; f <= D; ++f) {
-            const int64_t ef = (int64_t)f * L.N + v;
-            if (MODE == MODE_RESID)
-                y[ef] = (BLK == BLOCK_FULL || f < D) ? (T)((C)b[ef] - out[f]) : (T)0.0f;
-            else
-                y[ef] = (T)out[f];
+                for (int f = 0; f <= D; ++f) {
+                    const int64_t ef = (int64_t)f * L.N + v;
+                    if (MODE == MODE_RESID)
+                        y[ef] = (BLK == BLOCK_FULL || f < D) ? (T)((C)b[ef] - out[f]) : (T)0.0f;
+                    else
+                        y[ef] = (T)out[f];
+                }
+            }
         }
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            av[0][l] = av[1][l]; av[1][l] = av[2][l]; av[2][l] = 0;
+            bt[0][l] = bt[1][l]; bt[1][l] = bt[2][l]; bt[2][l] = 0;
+        }
+        dv[0] = dv[1]; dv[1] = dv[2]; dv[2] = 0;
+        cp[0] = cp[1]; cp[1] = cp[2]; cp[2] = 0;
     });
 }
 
