@@ -208,3 +208,24 @@ def test_default_path_is_merged_at_small_sizes():
     assert c["gs_vel_merged"] == 7 and c["p_rhs_merged"] == 1 and c["gs_p_merged"] == 3, c
     assert c["gs_vel_bulk"] == c["p_rhs_grouped"] == c["gs_p_bulk"] == 0, c
     P.close()
+
+
+def test_smoother_step_large_path_65():
+    """One interface-form smoothing step on the 65^3 sinker through the
+    large-level kernels.  Its special-row lists span 33 (velocity, interior
+    rows) to 129 (pressure, one-wave groups) workgroups per colour, so the
+    special-only kernels hand the XCDs permuted runs of 2 and 4 workgroups
+    (the smaller cases above stay below the 16 workgroups from which the
+    mapping permutes the velocity lists)."""
+    w = small_workload("sinker_3d", 5)
+    P = gpu_problem(w, merge_max_n=0)
+    lv = mg.Level(3, w["n"], w["inclusions"], w["mu"], "interface")
+    x = iss_inputs.random_vector(3, w["n"], seed=136)
+    b = iss_inputs.random_rhs(3, w["n"], seed=137)
+    xg = to_dev(x)
+    P.launch_counts(reset=True)
+    P.smooth("interface", xg, to_dev(b), nsteps=1)
+    c = P.launch_counts()
+    assert c["gs_vel_special"] == 7 and c["gs_p_special"] == 4 and c["gs_vel_merged"] == 0, c
+    assert _rel(to_host(xg), mg.smooth(lv, x, b, 1)) < 1e-11
+    P.close()
