@@ -148,34 +148,15 @@ print(json.dumps({'seconds': dt, 'its': len(h) - 1, 'relres': float(h[-1])}))
 """
 
 
-def full_solves(Problem, args, mid_form, coarse_form, forms, rhs_seed=177):
-    """Complete solves to 1e-8 of the two small workloads, measured on both
-    sides, nothing scaled: the GPU (median of 3 after one warm-up) and the
-    oracle on one host core per form (one run; setup and assembly
-    excluded).  The 65^2 split square (mu 10 / 1, seeded U[-1, 1] forcing)
-    with the plain multigrid of Sec. 5 (FGMRES(150) around one V(3,3)
-    cycle, omega 0.3, each form on every level); the 65^3 sphere (mu 1e3,
-    buoyancy) with the benchmark's solver."""
+def _gpu_full_solves(Problem, name, cfg, args, forms, rhs_seed):
+    """GPU leg of full_solves: median of 3 timed solves after one warm-up."""
     import torch
     import iss_inputs
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    bench_cfg = dict(omega=args.omega, nu=args.nu, nu_inc=args.nu_inc, cycles=args.cycles, mid_form=mid_form,
-                     coarse_form=coarse_form)
-    plain_cfg = dict(omega=0.3, nu=3, nu_inc=0, cycles=1, mid_form=None, coarse_form=None)
-    out = {}
-    for name, label, cfg in (("square_split_2d", "square_split_2d 65^2 mu 10/1", plain_cfg),
-                             ("sphere_3d", "sphere_3d 65^3 mu 1e3", bench_cfg)):
-        procs = {}
-        for form in forms:          # the oracle runs in the background while the GPU solves
-            src = ORACLE_SOLVE % (ROOT, name, form, cfg["omega"], cfg["nu"], cfg["nu"], cfg["coarse_form"],
-                                  cfg["mid_form"], cfg["nu_inc"], rhs_seed, args.restart, args.maxit,
-                                  cfg["cycles"])
-            procs[form] = subprocess.Popen([sys.executable, "-c", src], stdout=subprocess.PIPE,
-                                           stderr=subprocess.PIPE, text=True, env=env)
-        w = iss_inputs.workload(name)
-        P = Problem.from_workload(w, outer="fgmres", restart=args.restart, coarse_mu="average", nu1=cfg["nu"],
-                                  nu2=cfg["nu"], nu_inc=cfg["nu_inc"], omega=cfg["omega"],
-                                  coarse_form=cfg["coarse_form"], mid_form=cfg["mid_form"], cycles=cfg["cycles"])
+    w = iss_inputs.workload(name)
+    P = Problem.from_workload(w, outer="fgmres", restart=args.restart, coarse_mu="average", nu1=cfg["nu"],
+                              nu2=cfg["nu"], nu_inc=cfg["nu_inc"], omega=cfg["omega"],
+                              coarse_form=cfg["coarse_form"], mid_form=cfg["mid_form"], cycles=cfg["cycles"])
+    try:
         if w["buoyant"]:
             b = torch.zeros(P.vector_size(), dtype=torch.float64, device="cuda")
             P.rhs_buoyancy(b, w["buoyant"])
@@ -195,7 +176,40 @@ def full_solves(Problem, args, mid_form, coarse_form, forms, rhs_seed=177):
                     times.append(time.perf_counter() - t)
             res[form] = {"gpu_seconds": sorted(times)[1], "gpu_iterations": info["iterations"],
                          "gpu_relres": info["relres"]}
+        return res
+    finally:
         P.close()
+
+
+def full_solves(Problem, args, mid_form, coarse_form, forms, rhs_seed=177):
+    """Complete solves to 1e-8 of the two small workloads, measured on both
+    sides, nothing scaled: the GPU (median of 3 after one warm-up) and the
+    oracle on one host core per form (one run; setup and assembly
+    excluded).  The 65^2 split square (mu 10 / 1, seeded U[-1, 1] forcing)
+    with the plain multigrid of Sec. 5 (FGMRES(150) around one V(3,3)
+    cycle, omega 0.3, each form on every level); the 65^3 sphere (mu 1e3,
+    buoyancy) with the benchmark's solver."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    bench_cfg = dict(omega=args.omega, nu=args.nu, nu_inc=args.nu_inc, cycles=args.cycles, mid_form=mid_form,
+                     coarse_form=coarse_form)
+    plain_cfg = dict(omega=0.3, nu=3, nu_inc=0, cycles=1, mid_form=None, coarse_form=None)
+    out = {}
+    for name, label, cfg in (("square_split_2d", "square_split_2d 65^2 mu 10/1", plain_cfg),
+                             ("sphere_3d", "sphere_3d 65^3 mu 1e3", bench_cfg)):
+        procs = {}
+        for form in forms:          # the oracle runs in the background while the GPU solves
+            src = ORACLE_SOLVE % (ROOT, name, form, cfg["omega"], cfg["nu"], cfg["nu"], cfg["coarse_form"],
+                                  cfg["mid_form"], cfg["nu_inc"], rhs_seed, args.restart, args.maxit,
+                                  cfg["cycles"])
+            procs[form] = subprocess.Popen([sys.executable, "-c", src], stdout=subprocess.PIPE,
+                                           stderr=subprocess.PIPE, text=True, env=env)
+        try:
+            res = _gpu_full_solves(Problem, name, cfg, args, forms, rhs_seed)
+        except BaseException:
+            for pr in procs.values():       # no oracle run outlives a failed GPU leg
+                pr.kill()
+                pr.wait()
+            raise
         for form, pr in procs.items():
             so, se = pr.communicate(timeout=900)
             if pr.returncode != 0:
