@@ -597,7 +597,7 @@ def main():
     # per interior vertex.  The whole smoothing step is charged the
     # symmetric sweep (162 B) plus the pressure Uzawa step (u, p, g read,
     # p written, phase: 49 B) = 211 B per interior vertex.
-    roof = roof_step = None
+    roof = roof_step = roof_phase = None
     if smooth_ms:
         n_int = (w["n"] - 1) ** w["dim"]
         bytes_launch = 81.0 / (w["dim"] + 1) * n_int
@@ -608,6 +608,17 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_launch, "bytes_per_vertex_per_sweep": 81,
                 "ms_per_launch": ms, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic("k_gs_vel_s", main_form)}
+        # the same launch charged what one colour phase on its own must
+        # move: every colour neighbours every other in the Kuhn stencil, so
+        # all of u is read (24 B per vertex), besides the own colour's g
+        # and phase byte, and the own colour's u is written (24 + (24 + 1 +
+        # 24) / (d + 1) B per interior vertex in 3D)
+        M = w["dim"] + 1
+        phase_bytes = (8.0 * w["dim"] + (16.0 * w["dim"] + 1) / M) * n_int
+        roof_phase = {"bound": "hbm", "what": "the same launch, bytes a single colour phase must move",
+                      "bytes_per_launch": phase_bytes, "ms_per_launch": ms,
+                      "achieved": phase_bytes / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": phase_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
         step_bytes = 211.0 * n_int
         st = smooth_ms[main_form]["step_ms"]
         roof_step = {"bound": "hbm", "what": "one Uzawa smoothing step, finest level, FP64, all kernels",
@@ -653,6 +664,7 @@ def main():
         "asymptotic_rate": rates,
         "roofline": roof,
         "roofline_smoothing_step": roof_step,
+        "roofline_colour_phase_minimum": roof_phase,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
