@@ -236,6 +236,20 @@ def test_colouring_has_no_same_colour_coupling(form):
     assert not ((vi != vj) & (c2[vi] == c2[vj]) & (np.abs(K2.data) > 0)).any()
 
 
+def test_every_colour_neighbours_every_other():
+    """In 3D every interior vertex is coupled through the velocity block to
+    vertices of all three other colours, so one colour phase of the smoother
+    reads every colour of u (the bytes a single phase must move)."""
+    D = disc(3, 6, 1e3)
+    col = mg.colours(3, 6)
+    A = D.stokes("strain").tocsr()[:D.N, :D.N]
+    interior = np.flatnonzero(~D.boundary)
+    for v in interior:
+        lo, hi = A.indptr[v], A.indptr[v + 1]
+        nb = A.indices[lo:hi][(A.indices[lo:hi] != v) & (A.data[lo:hi] != 0)]
+        assert set(((col[nb] - col[v]) % 4).tolist()) == {1, 2, 3}, v
+
+
 def test_smoother_equals_triangular_solves():
     """One Uzawa step (eq. Uzawa_smooth) equals: a forward then a backward
     triangular solve of the velocity block in (colour, component) order and
