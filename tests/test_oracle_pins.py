@@ -242,12 +242,13 @@ def test_every_colour_neighbours_every_other():
     reads every colour of u (the bytes a single phase must move)."""
     D = disc(3, 6, 1e3)
     col = mg.colours(3, 6)
-    A = D.stokes("strain").tocsr()[:D.N, :D.N]
     interior = np.flatnonzero(~D.boundary)
-    for v in interior:
-        lo, hi = A.indptr[v], A.indptr[v + 1]
-        nb = A.indices[lo:hi][(A.indices[lo:hi] != v) & (A.data[lo:hi] != 0)]
-        assert set(((col[nb] - col[v]) % 4).tolist()) == {1, 2, 3}, v
+    for form in ("interface", "strain"):
+        A = D.stokes(form).tocsr()[:D.N, :D.N]
+        for v in interior:
+            lo, hi = A.indptr[v], A.indptr[v + 1]
+            nb = A.indices[lo:hi][(A.indices[lo:hi] != v) & (A.data[lo:hi] != 0)]
+            assert set(((col[nb] - col[v]) % 4).tolist()) == {1, 2, 3}, (form, v)
 
 
 def test_smoother_equals_triangular_solves():
