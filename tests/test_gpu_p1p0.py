@@ -113,3 +113,22 @@ def test_p1p0_with_per_element_phases():
 
 def mesh_elements_sorted(E):
     return np.sort(np.asarray(E), axis=1)
+
+
+@pytest.mark.parametrize("case", [("sphere_3d", 4, None, "noslip"), ("columns_3d", 2, 4, "freeslip")],
+                         ids=["sphere_3d-L4-noslip", "columns_3d-L2-m4-freeslip"])
+@pytest.mark.parametrize("form", ["interface", "strain"])
+def test_p1p0_apply_through_the_tiled_velocity_apply(case, form):
+    """The velocity part of the P1-P0 apply through the LDS-tiled z-march of
+    the large levels (merge_max_n = 0; 17^3, two z chunks), as at 257^3."""
+    import torch
+    w = _case(*case)
+    d, n = w["dim"], w["n"]
+    P = gpu_problem(w, merge_max_n=0)
+    O = p1p0.P1P0(d, n, w["inclusions"], w["mu"], gamma=1.0, bc=w["bc"])
+    x = np.random.default_rng(174).uniform(-1, 1, O.ndof) * O.free_mask()
+    K = O.stokes(form)
+    y = torch.empty(O.ndof, dtype=torch.float64, device="cuda")
+    P.p1p0_apply(form, to_dev(x), y, gamma=1.0)
+    assert_close_scaled(to_host(y), K @ x, abs_scale(K, x), 1e-12, "%s P1-P0 apply, tiled" % form)
+    P.close()
