@@ -251,6 +251,45 @@ def test_every_colour_neighbours_every_other():
             assert set(((col[nb] - col[v]) % 4).tolist()) == {1, 2, 3}, (form, v)
 
 
+def _point_gs(lv, x, b, groups):
+    """Point-block Gauss-Seidel on the velocity block: every vertex of each
+    group in turn solves its d x d block for its residual (fixed velocity
+    entries stay)."""
+    A, N, d = lv.A.tocsr(), lv.N, lv.dim
+    free = lv.free[:d * N].reshape(d, N)
+    for verts in groups:
+        for v in verts:
+            idx = np.array([v + k * N for k in range(d) if free[k, v]])
+            if len(idx) == 0:
+                continue
+            r = b[idx] - A[idx] @ x
+            x[idx] += np.linalg.solve(A[idx][:, idx].toarray(), r)
+    return x
+
+
+@pytest.mark.parametrize("form", ["interface", "strain"])
+def test_z_wavefront_colour_order_equals_the_colour_sweep(form):
+    """A forward colour sweep (colour 0 everywhere, then 1, 2, 3) gives the
+    same iterate, bit for bit, as the z-wavefront order of a fused sweep
+    (step t: colour 0 on plane t, colour 1 on plane t - 1, colour 2 on
+    plane t - 2, colour 3 on plane t - 3): every vertex update reads the
+    same values in both orders."""
+    n = 6
+    lv = mg.Level(3, n, [{'kind': 'sphere', 'center': (0.5, 0.45, 0.55), 'radius': 0.3, 'phase': 1}],
+                  [1.0, 100.0], form)
+    ijk = mesh.vertex_ijk(3, n)
+    col = lv.colour
+    rng = np.random.default_rng(5)
+    x0 = rng.uniform(-1, 1, 3 * lv.N) * lv.free[:3 * lv.N]
+    b = rng.uniform(-1, 1, 3 * lv.N) * lv.free[:3 * lv.N]
+    phases = [np.flatnonzero(col == c) for c in range(4)]
+    wave = [np.flatnonzero((col == c) & (ijk[:, 2] == t - c)) for t in range(n + 4) for c in range(4)]
+    xa = _point_gs(lv, x0.copy(), b, phases)
+    xb = _point_gs(lv, x0.copy(), b, wave)
+    assert np.array_equal(xa, xb)
+    assert not np.array_equal(xa, x0)
+
+
 def test_smoother_equals_triangular_solves():
     """One Uzawa step (eq. Uzawa_smooth) equals: a forward then a backward
     triangular solve of the velocity block in (colour, component) order and
